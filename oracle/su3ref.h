@@ -1,0 +1,105 @@
+/*
+ * su3ref.h -- plain FP64 CPU oracle for the checkerboard SU(3) heat-bath sweep.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously-correct
+ * reference that the GPU path is checked against.  Only the test suite, the
+ * package smoke test and the CPU-baseline leg of the benchmark may load it.
+ * It shares no source with the GPU library (paper_0904_1179_amd/csrc, include/).
+ *
+ * Method: Berg & Wu, "Fortran MPI Checkerboard Code for SU(3) Lattice Gauge
+ * Theory II".  The paper times nequi checkerboard heat-bath sweeps of pure
+ * SU(3) Wilson-action LGT (Sec. 2, eq. (1)) on periodic (nlat=1) and
+ * double-layered-torus (nlat=2) lattices (Sec. 1, Table 1), storing every link
+ * as 18 reals (App. A, eq. (4)).  The paper prints no formula for the action,
+ * the staple, the heat bath or the DLT gluing; the definitions used here are
+ * the standard ones, stated next to each function in su3ref.c.
+ *
+ * Canonical link layout (host, FP64): links[(4*site + mu)*18 + (3*row+col)*2 + reim]
+ * with site = layer*V + x0 + L0*(x1 + L1*(x2 + L2*x3)), V = L0*L1*L2*L3.
+ */
+#ifndef SU3REF_H
+#define SU3REF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t  L[4];       /* extents; each even and >= 2 */
+    int32_t  nlat;       /* 1 = periodic torus, 2 = double-layered torus */
+    uint32_t flip_mask;  /* nlat=2: bit mu set => crossing the mu boundary switches layer */
+    int32_t  nhit;       /* Kennedy-Pendleton attempts per SU(2) subgroup (1 = 1-hit) */
+    uint64_t seed;       /* Philox key word 0 */
+} su3ref_params;
+
+typedef struct su3ref_lattice su3ref_lattice;
+
+/* 0 if the parameters are valid, -1 otherwise. */
+int su3ref_check_params(const su3ref_params *p);
+
+/* Allocate a lattice (host memory).  NULL on invalid parameters. */
+su3ref_lattice *su3ref_create(const su3ref_params *p);
+void su3ref_destroy(su3ref_lattice *lat);
+
+/* Number of doubles in the canonical link array (18 * 4 * V * nlat). */
+int64_t su3ref_n_doubles(const su3ref_lattice *lat);
+double *su3ref_links(su3ref_lattice *lat);
+
+/* hot = 0: every link the identity; hot = 1: Haar-random links.  Resets the
+ * sweep counter and the heat-bath counters. */
+void su3ref_start(su3ref_lattice *lat, int hot);
+
+/* n sweeps at coupling beta.  nthreads <= 0: OpenMP default.  order_seed = 0:
+ * links of a pass in lexicographic order; otherwise a shuffled order (a pass
+ * updates mutually independent links, so the result must not change). */
+void su3ref_sweep(su3ref_lattice *lat, int n, double beta, int nthreads, uint64_t order_seed);
+
+/* out[0] = mean plaquette 1/3 Re Tr U_P over the lattice, out[1..nlat] per
+ * layer (a plaquette belongs to the layer of its base site). */
+void su3ref_plaquette(const su3ref_lattice *lat, double *out);
+
+void su3ref_reunitarise(su3ref_lattice *lat);
+
+uint64_t su3ref_get_sweeps(const su3ref_lattice *lat);
+void su3ref_set_sweeps(su3ref_lattice *lat, uint64_t s);
+void su3ref_counters(const su3ref_lattice *lat, uint64_t *attempts, uint64_t *accepts);
+
+/* U_mu(x) -> g(x) U_mu(x) g(x+mu)^dagger with Haar g(x) drawn from key gseed. */
+void su3ref_gauge_transform(su3ref_lattice *lat, uint64_t gseed);
+
+/* Geometry. */
+int64_t su3ref_volume(const su3ref_lattice *lat);
+int64_t su3ref_neighbor(const su3ref_lattice *lat, int64_t site, int mu, int dir);
+int su3ref_parity(const su3ref_lattice *lat, int64_t site);
+/* The 18 link ids of the staple of link (site, mu), in the order documented in su3ref.c. */
+void su3ref_staple_lids(const su3ref_lattice *lat, int64_t site, int mu, int64_t *lids18);
+void su3ref_staple(const su3ref_lattice *lat, int64_t site, int mu, double *A18);
+
+/* Single-link primitives (all matrices 18 doubles, row-major complex). */
+void su3ref_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+void su3ref_hot_link(uint64_t seed, uint64_t lid, double *U);
+/* The Haar gauge element g(site) used by su3ref_gauge_transform. */
+void su3ref_gauge_element(uint64_t gseed, uint64_t site, double *g);
+void su3ref_staple_from_links(const double *nb, double *A);  /* nb: 18 matrices */
+void su3ref_reunit(double *U);
+/* One heat-bath update of U (3 subgroups + reunitarisation) given its staple A.
+ * cnt[0] += attempts, cnt[1] += accepts. */
+void su3ref_heatbath_link(double *U, const double *A, double beta, uint64_t seed,
+                          uint64_t lid, uint64_t sweep, int nhit, uint64_t *cnt);
+/* n Kennedy-Pendleton draws at strength alpha, attempt cap `cap` per draw.
+ * Draw i uses the heat-bath counters of link id i, sweep 0, subgroup 0.
+ * a[4*i..4*i+3] = sampled SU(2) element (a0, a1, a2, a3); NaN if the cap was hit.
+ * Returns the number of draws that hit the cap; *tries = total attempts. */
+int64_t su3ref_kp_draws(double alpha, uint64_t seed, int64_t n, int cap, double *a, int64_t *tries);
+/* A chain of nsteps heat-bath updates of one link in the fixed staple A.
+ * obs[t] = 1/3 Re Tr(U A) after step t. */
+void su3ref_single_link_chain(double *U, const double *A, double beta, uint64_t seed,
+                              int64_t nsteps, int nhit, double *obs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
