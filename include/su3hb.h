@@ -1,0 +1,150 @@
+/*
+ * su3hb.h -- C ABI of the MI355X (gfx950) checkerboard SU(3) heat-bath library.
+ *
+ * What it computes (Berg & Wu, "Fortran MPI Checkerboard Code for SU(3)
+ * Lattice Gauge Theory II"): nequi checkerboard updating sweeps of pure SU(3)
+ * lattice gauge theory with the Wilson action, S = beta sum_P (1 - 1/3 Re Tr U_P),
+ * on a periodic 4D torus (nlat = 1) or a double-layered torus (nlat = 2)
+ * (Sec. 1; Sec. 2, eq. (1) and the nequi/lswp description; Table 1).  Every
+ * link is an SU(3) matrix of 18 reals (App. A, eq. (4)); the paper reports the
+ * cost per SU(3) matrix update (Sec. 2.1, Fig. 1), which is the unit of this
+ * library's throughput.  A sweep is 8 checkerboard passes (direction mu = 0..3,
+ * parity even then odd); each updated link gets the Cabibbo-Marinari heat bath
+ * in its SU(2) subgroups (0,1), (1,2), (0,2) with nhit Kennedy-Pendleton
+ * attempts per subgroup ("1-hit" for nhit = 1, Sec. 2.1) and is then
+ * reunitarised.  Random numbers are Philox4x64-10 keyed by (seed; link id,
+ * sweep index, subgroup/attempt, purpose), so a result does not depend on the
+ * launch configuration, and resuming from a checkpoint is exact.
+ *
+ * Memory ownership: the caller allocates the device buffers (sizes from
+ * su3_footprint) and the HIP stream; the library never allocates or frees
+ * device memory.  All calls enqueue on the stream given to su3_create and
+ * return without waiting, except su3_plaquette, su3_get_links, su3_set_links,
+ * su3_counters and su3_profile_read, which synchronise that stream.
+ *
+ * Errors: every call returns an su3_status; nothing aborts or throws across
+ * the ABI.  su3_last_error() gives a thread-local description of the last
+ * failure.  A launch or asynchronous device fault is reported as SU3_EDEVICE
+ * by the call that detects it.
+ *
+ * Threading: one context per stream.  Distinct contexts are independent and
+ * may be used from different threads; one context must not be used from two
+ * threads at once.
+ */
+#ifndef SU3HB_H
+#define SU3HB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SU3_OK = 0,
+    SU3_EINVAL = -1,  /* invalid argument (parameters, sizes, null pointers, beta) */
+    SU3_ENOSPC = -2,  /* a caller buffer is smaller than su3_footprint requires */
+    SU3_EDEVICE = -3, /* HIP launch or runtime error */
+    SU3_ESTATE = -4   /* call out of order, e.g. sweep or plaquette before start */
+} su3_status;
+
+typedef struct su3_ctx su3_ctx;
+
+typedef struct {
+    int32_t L[4];       /* lattice extents L0..L3 (the paper's nl1..nl4); each even, 2 <= L <= 1024,
+                           nlat*L0*L1*L2*L3 <= 2^30 */
+    int32_t nlat;       /* 1 = periodic torus, 2 = double-layered torus (Table 1, nlat) */
+    uint32_t flip_mask; /* nlat = 2: bit mu set => stepping across the mu boundary moves to the other
+                           layer (default reading 0x7: the three partitioned directions of Table 3);
+                           must be 0 for nlat = 1 */
+    int32_t precision;  /* 64: links stored and multiplied in FP64.
+                           32: links stored and multiplied in FP32; reunitarisation, plaquette
+                           products and all global sums in FP64 */
+    int32_t nhit;       /* Kennedy-Pendleton attempts per SU(2) subgroup, >= 1 (1 = 1-hit) */
+    uint64_t seed;      /* Philox key */
+} su3_params;
+
+/* Device bytes the caller must provide for the links and the scratch area.
+ * Links: 72 component planes (4 directions x 2 parities x 9 complex entries),
+ * each of round_up(nlat*V/2, 64) complex numbers of the link precision.
+ * Scratch: plaquette partial sums and heat-bath counters (a few hundred kB).
+ * SU3_EINVAL on invalid parameters. */
+su3_status su3_footprint(const su3_params *p, size_t *link_bytes, size_t *scratch_bytes);
+
+/* Bind a context to caller-owned device memory and a hipStream_t (NULL = the
+ * null stream).  d_links and d_scratch must be device pointers, 256-byte
+ * aligned, of at least the footprint sizes (else SU3_ENOSPC).  Parameters are
+ * validated before any HIP call.  The links are undefined until su3_start or
+ * su3_set_links. */
+su3_status su3_create(const su3_params *p, void *d_links, size_t link_bytes, void *d_scratch,
+                      size_t scratch_bytes, void *hip_stream, su3_ctx **out);
+
+/* Start configuration (Sec. 2: created before the timed sweeps and excluded
+ * from the timing).  hot = 0: every link the identity; hot = 1: Haar-random
+ * links.  Resets the sweep counter and the heat-bath counters. */
+su3_status su3_start(su3_ctx *c, int32_t hot);
+
+/* Enqueue n >= 0 sweeps at coupling beta (finite, > 0).  The sweep counter
+ * advances by n; it keys the random numbers, so sweep(a) then sweep(b) equals
+ * sweep(a + b) bit for bit.  SU3_ESTATE before su3_start/su3_set_links. */
+su3_status su3_sweep(su3_ctx *c, int32_t n, double beta);
+
+/* Mean plaquette 1/3 Re Tr U_P: out[0] over the whole lattice, out[1..nlat] per
+ * layer (a plaquette belongs to the layer of its base site).  n >= 1 + nlat.
+ * Accumulated in FP64 with a fixed reduction order (bitwise reproducible).
+ * Synchronises the stream. */
+su3_status su3_plaquette(su3_ctx *c, double *out, int32_t n);
+
+/* Project every link back onto SU(3) (Gram-Schmidt of rows 0 and 1, row 2 =
+ * conj(row0 x row1)), in FP64 for both precisions.  The heat bath already does
+ * this for every link it updates. */
+su3_status su3_reunitarise(su3_ctx *c);
+
+/* Copy the links to / from host memory in the canonical FP64 layout
+ * host[(4*site + mu)*18 + (3*row + col)*2 + reim], site = layer*V + lex,
+ * lex = x0 + L0*(x1 + L1*(x2 + L2*x3)).  n_doubles must be 72*V*nlat.
+ * For precision 32 the values are widened / rounded to FP32.  Synchronise the
+ * stream.  su3_set_links also marks the context started. */
+su3_status su3_get_links(su3_ctx *c, double *host, size_t n_doubles);
+su3_status su3_set_links(su3_ctx *c, const double *host, size_t n_doubles);
+
+/* Copy the n links with canonical ids lids[k] = 4*site + mu (site as above) to
+ * host[18*k .. 18*k+17], same element order as su3_get_links: a sampled check
+ * of a lattice too large to copy whole.  SU3_EINVAL for an id out of range.
+ * Synchronises the stream. */
+su3_status su3_get_link_sample(su3_ctx *c, const uint64_t *lids, size_t n, double *host);
+
+/* Sweep counter (the sweep index of the next sweep) for checkpoint / resume. */
+su3_status su3_get_sweep_index(su3_ctx *c, uint64_t *sweep_index);
+su3_status su3_set_sweep_index(su3_ctx *c, uint64_t sweep_index);
+
+/* Sweeps done since start and Kennedy-Pendleton attempts / acceptances (exact
+ * integer counts).  Any pointer may be NULL.  Synchronises the stream. */
+su3_status su3_counters(su3_ctx *c, uint64_t *sweeps, uint64_t *kp_attempts, uint64_t *kp_accepts);
+
+/* Random gauge transformation U_mu(x) -> g(x) U_mu(x) g(x+mu)^+ with Haar g
+ * drawn from key gseed (a test of gauge invariance; not part of a sweep). */
+su3_status su3_gauge_transform(su3_ctx *c, uint64_t gseed);
+
+/* Per-pass timing: while enabled, every heat-bath pass launch is bracketed by
+ * HIP events on the context's stream.  su3_profile_read synchronises and
+ * returns the summed pass time in ms and the number of passes timed since the
+ * last read (then resets both). */
+su3_status su3_profile(su3_ctx *c, int32_t enable);
+su3_status su3_profile_read(su3_ctx *c, double *total_ms, uint64_t *passes);
+
+/* Releases the context (host memory and events); never frees caller memory. */
+su3_status su3_destroy(su3_ctx *c);
+
+/* Bandwidth probe: copy `bytes` (multiple of 16) from src to dst on the given
+ * stream with 16-byte vector loads and stores.  Asynchronous. */
+su3_status su3_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+const char *su3_strerror(su3_status s);
+const char *su3_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,518 @@
+// api.hip -- host runtime behind the C ABI declared in include/su3hb.h.
+//
+// The context binds caller-owned device buffers and a stream; every entry
+// point validates its arguments before touching HIP, enqueues work on the
+// context's stream and reports failures as su3_status plus a thread-local
+// message.  A sweep is the 8-pass schedule mu = 0..3 x parity (even, odd),
+// each pass one k_update launch; the sweep index keys the random numbers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/su3hb.h"
+#include "launch.h"
+
+using su3hb::Geom;
+
+struct su3_ctx {
+    su3_params p;
+    Geom g;
+    size_t V;
+    void *links;
+    size_t link_bytes;
+    unsigned char *scratch;
+    size_t scratch_bytes;
+    hipStream_t stream;
+    bool started;
+    uint64_t sweep_index;  // index of the next sweep (keys the random numbers)
+    uint64_t sweeps_done;  // since the last start
+    // profiling
+    bool profile;
+    std::vector<hipEvent_t> ev;  // pairs (start, stop)
+    size_t ev_used;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+su3_status fail(su3_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+su3_status hip_fail(hipError_t e, const char *where)
+{
+    return fail(SU3_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// scratch layout (bytes): [0, 16) heat-bath counters (2 x u64);
+// [256, 256 + 8*(1+nlat)) plaquette sums; [512, ...) plaquette partials
+constexpr size_t kOffCounters = 0;
+constexpr size_t kOffSums = 256;
+constexpr size_t kOffPartials = 512;
+
+long long round_up(long long a, long long m) { return (a + m - 1) / m * m; }
+
+su3_status check_params(const su3_params *p)
+{
+    if (!p) return fail(SU3_EINVAL, "params is NULL");
+    for (int mu = 0; mu < 4; ++mu) {
+        const int L = p->L[mu];
+        if (L < 2 || L > 1024 || (L & 1))
+            return fail(SU3_EINVAL, "L[" + std::to_string(mu) + "] = " + std::to_string(L) +
+                                        ": extents must be even and in [2, 1024]");
+    }
+    if (p->nlat != 1 && p->nlat != 2) return fail(SU3_EINVAL, "nlat must be 1 (torus) or 2 (double-layered torus)");
+    if (p->nlat == 1 && p->flip_mask != 0) return fail(SU3_EINVAL, "flip_mask must be 0 when nlat = 1");
+    if (p->flip_mask > 0xF) return fail(SU3_EINVAL, "flip_mask has bits above direction 3");
+    if (p->precision != 64 && p->precision != 32) return fail(SU3_EINVAL, "precision must be 64 or 32");
+    if (p->nhit < 1 || p->nhit > 64) return fail(SU3_EINVAL, "nhit must be in [1, 64]");
+    const long long V = (long long)p->L[0] * p->L[1] * p->L[2] * p->L[3];
+    if ((long long)p->nlat * V > (1LL << 30))
+        return fail(SU3_EINVAL, "lattice too large: nlat*V must not exceed 2^30 sites");
+    return SU3_OK;
+}
+
+Geom make_geom(const su3_params *p)
+{
+    Geom g;
+    for (int mu = 0; mu < 4; ++mu) g.L[mu] = p->L[mu];
+    const long long V = (long long)p->L[0] * p->L[1] * p->L[2] * p->L[3];
+    g.Vh = (int)(V / 2);
+    g.nlat = p->nlat;
+    g.flip = p->nlat == 2 ? p->flip_mask : 0u;
+    g.stride = round_up((long long)p->nlat * (V / 2), 64);
+    return g;
+}
+
+size_t link_bytes_of(const su3_params *p, const Geom &g)
+{
+    return (size_t)72 * (size_t)g.stride * (p->precision == 64 ? 16u : 8u);
+}
+
+size_t scratch_bytes_of(const Geom &g)
+{
+    return (size_t)round_up(kOffPartials + 8LL * g.nlat * su3hb::plaq_blocks(g), 256);
+}
+
+su3_status check_ctx(su3_ctx *c)
+{
+    if (!c) return fail(SU3_EINVAL, "context is NULL");
+    return SU3_OK;
+}
+
+su3_status check_started(su3_ctx *c)
+{
+    if (!c->started) return fail(SU3_ESTATE, "links are undefined: call su3_start or su3_set_links first");
+    return SU3_OK;
+}
+
+unsigned long long *counters_of(su3_ctx *c) { return (unsigned long long *)(c->scratch + kOffCounters); }
+
+// canonical host index of the plane element (dir, par, e, n): maps (layer, parity, i) to site
+void site_of_elem(const Geom &g, int par, long long n, long long *site)
+{
+    const int layer = n >= g.Vh ? 1 : 0;
+    long long i = n - (long long)layer * g.Vh;
+    const int l0h = g.L[0] / 2;
+    long long r = i / l0h;
+    const int x0h = (int)(i - r * l0h);
+    const int x1 = (int)(r % g.L[1]);
+    r /= g.L[1];
+    const int x2 = (int)(r % g.L[2]);
+    const int x3 = (int)(r / g.L[2]);
+    const int x0 = 2 * x0h + ((par + x1 + x2 + x3) & 1);
+    const long long lex = x0 + (long long)g.L[0] * (x1 + (long long)g.L[1] * (x2 + (long long)g.L[2] * x3));
+    *site = (long long)layer * 2LL * g.Vh + lex;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *su3_strerror(su3_status s)
+{
+    switch (s) {
+    case SU3_OK: return "success";
+    case SU3_EINVAL: return "invalid argument";
+    case SU3_ENOSPC: return "buffer smaller than the footprint";
+    case SU3_EDEVICE: return "HIP device error";
+    case SU3_ESTATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+const char *su3_last_error(void) { return g_last_error.c_str(); }
+
+su3_status su3_footprint(const su3_params *p, size_t *link_bytes, size_t *scratch_bytes)
+{
+    su3_status st = check_params(p);
+    if (st != SU3_OK) return st;
+    const Geom g = make_geom(p);
+    if (link_bytes) *link_bytes = link_bytes_of(p, g);
+    if (scratch_bytes) *scratch_bytes = scratch_bytes_of(g);
+    return SU3_OK;
+}
+
+su3_status su3_create(const su3_params *p, void *d_links, size_t link_bytes, void *d_scratch, size_t scratch_bytes,
+                      void *hip_stream, su3_ctx **out)
+{
+    if (!out) return fail(SU3_EINVAL, "out is NULL");
+    *out = nullptr;
+    su3_status st = check_params(p);
+    if (st != SU3_OK) return st;
+    if (!d_links || !d_scratch) return fail(SU3_EINVAL, "device buffers must not be NULL");
+    if (((uintptr_t)d_links & 255u) || ((uintptr_t)d_scratch & 255u))
+        return fail(SU3_EINVAL, "device buffers must be 256-byte aligned");
+    const Geom g = make_geom(p);
+    if (link_bytes < link_bytes_of(p, g))
+        return fail(SU3_ENOSPC, "link buffer has " + std::to_string(link_bytes) + " bytes, needs " +
+                                    std::to_string(link_bytes_of(p, g)));
+    if (scratch_bytes < scratch_bytes_of(g))
+        return fail(SU3_ENOSPC, "scratch buffer has " + std::to_string(scratch_bytes) + " bytes, needs " +
+                                    std::to_string(scratch_bytes_of(g)));
+    su3_ctx *c = new (std::nothrow) su3_ctx();
+    if (!c) return fail(SU3_EINVAL, "out of host memory");
+    c->p = *p;
+    c->g = g;
+    c->V = (size_t)p->L[0] * p->L[1] * p->L[2] * p->L[3];
+    c->links = d_links;
+    c->link_bytes = link_bytes;
+    c->scratch = (unsigned char *)d_scratch;
+    c->scratch_bytes = scratch_bytes;
+    c->stream = (hipStream_t)hip_stream;
+    c->started = false;
+    c->sweep_index = 0;
+    c->sweeps_done = 0;
+    c->profile = false;
+    c->ev_used = 0;
+    *out = c;
+    return SU3_OK;
+}
+
+su3_status su3_destroy(su3_ctx *c)
+{
+    if (!c) return SU3_OK;
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    delete c;
+    return SU3_OK;
+}
+
+su3_status su3_start(su3_ctx *c, int32_t hot)
+{
+    su3_status st = check_ctx(c);
+    if (st != SU3_OK) return st;
+    if (hot != 0 && hot != 1) return fail(SU3_EINVAL, "hot must be 0 (cold) or 1 (hot)");
+    hipError_t e = su3hb::launch_start(c->p.precision, c->links, c->g, hot, c->p.seed, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "start kernel");
+    e = su3hb::launch_zero_u64(counters_of(c), 2, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "counter reset");
+    c->started = true;
+    c->sweep_index = 0;
+    c->sweeps_done = 0;
+    return SU3_OK;
+}
+
+su3_status su3_sweep(su3_ctx *c, int32_t n, double beta)
+{
+    su3_status st = check_ctx(c);
+    if (st != SU3_OK) return st;
+    if (n < 0) return fail(SU3_EINVAL, "n must be >= 0");
+    if (!std::isfinite(beta) || !(beta > 0.0)) return fail(SU3_EINVAL, "beta must be finite and > 0");
+    st = check_started(c);
+    if (st != SU3_OK) return st;
+    for (int32_t s = 0; s < n; ++s) {
+        for (int mu = 0; mu < 4; ++mu)
+            for (int par = 0; par < 2; ++par) {
+                if (c->profile) {
+                    while (c->ev_used + 2 > c->ev.size()) {
+                        hipEvent_t ev;
+                        hipError_t e = hipEventCreate(&ev);
+                        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+                        c->ev.push_back(ev);
+                    }
+                    hipError_t e = hipEventRecord(c->ev[c->ev_used], c->stream);
+                    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+                }
+                hipError_t e = su3hb::launch_update(c->p.precision, c->links, c->g, mu, par, beta, c->sweep_index,
+                                                    c->p.seed, c->p.nhit, counters_of(c), c->stream);
+                if (e != hipSuccess) return hip_fail(e, "update kernel");
+                if (c->profile) {
+                    e = hipEventRecord(c->ev[c->ev_used + 1], c->stream);
+                    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+                    c->ev_used += 2;
+                }
+            }
+        c->sweep_index += 1;
+        c->sweeps_done += 1;
+    }
+    return SU3_OK;
+}
+
+su3_status su3_plaquette(su3_ctx *c, double *out, int32_t n)
+{
+    su3_status st = check_ctx(c);
+    if (st != SU3_OK) return st;
+    if (!out || n < 1 + c->p.nlat) return fail(SU3_EINVAL, "out must hold 1 + nlat doubles");
+    st = check_started(c);
+    if (st != SU3_OK) return st;
+    double *sums = (double *)(c->scratch + kOffSums);
+    double *partials = (double *)(c->scratch + kOffPartials);
+    hipError_t e = su3hb::launch_plaquette(c->p.precision, c->links, c->g, partials, sums, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "plaquette kernels");
+    double h[3] = {0, 0, 0};
+    e = hipMemcpyAsync(h, sums, sizeof(double) * (1 + c->p.nlat), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "plaquette copy");
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "plaquette sync");
+    const double norm = 18.0 * (double)c->V;
+    out[0] = h[0] / (norm * c->p.nlat);
+    for (int l = 0; l < c->p.nlat; ++l) out[1 + l] = h[1 + l] / norm;
+    return SU3_OK;
+}
+
+su3_status su3_reunitarise(su3_ctx *c)
+{
+    su3_status st = check_ctx(c);
+    if (st != SU3_OK) return st;
+    st = check_started(c);
+    if (st != SU3_OK) return st;
+    hipError_t e = su3hb::launch_reunit(c->p.precision, c->links, c->g, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "reunitarise kernel");
+    return SU3_OK;
+}
+
+su3_status su3_gauge_transform(su3_ctx *c, uint64_t gseed)
+{
+    su3_status st = check_ctx(c);
+    if (st != SU3_OK) return st;
+    st = check_started(c);
+    if (st != SU3_OK) return st;
+    hipError_t e = su3hb::launch_gauge(c->p.precision, c->links, c->g, gseed, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "gauge kernel");
+    return SU3_OK;
+}
+
+su3_status su3_get_links(su3_ctx *c, double *host, size_t n_doubles)
+{
+    su3_status st = check_ctx(c);
+    if (st != SU3_OK) return st;
+    if (!host) return fail(SU3_EINVAL, "host buffer is NULL");
+    const size_t need = (size_t)72 * c->V * c->p.nlat;
+    if (n_doubles != need) return fail(SU3_EINVAL, "n_doubles must be 72*V*nlat = " + std::to_string(need));
+    st = check_started(c);
+    if (st != SU3_OK) return st;
+    const Geom &g = c->g;
+    const size_t bytes = link_bytes_of(&c->p, g);
+    std::vector<unsigned char> buf;
+    try {
+        buf.resize(bytes);
+    } catch (...) {
+        return fail(SU3_EINVAL, "out of host memory for the staging copy");
+    }
+    hipError_t e = hipMemcpyAsync(buf.data(), c->links, bytes, hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "link copy");
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "link copy sync");
+    const long long nelem = (long long)g.nlat * g.Vh;
+    for (int par = 0; par < 2; ++par)
+        for (long long n = 0; n < nelem; ++n) {
+            long long site;
+            site_of_elem(g, par, n, &site);
+            for (int dir = 0; dir < 4; ++dir) {
+                double *dst = host + (size_t)(4 * site + dir) * 18;
+                for (int el = 0; el < 9; ++el) {
+                    const size_t idx = (size_t)((dir * 2 + par) * 9 + el) * (size_t)g.stride + (size_t)n;
+                    if (c->p.precision == 64) {
+                        const double *v = (const double *)buf.data() + 2 * idx;
+                        dst[2 * el] = v[0];
+                        dst[2 * el + 1] = v[1];
+                    } else {
+                        const float *v = (const float *)buf.data() + 2 * idx;
+                        dst[2 * el] = (double)v[0];
+                        dst[2 * el + 1] = (double)v[1];
+                    }
+                }
+            }
+        }
+    return SU3_OK;
+}
+
+su3_status su3_set_links(su3_ctx *c, const double *host, size_t n_doubles)
+{
+    su3_status st = check_ctx(c);
+    if (st != SU3_OK) return st;
+    if (!host) return fail(SU3_EINVAL, "host buffer is NULL");
+    const size_t need = (size_t)72 * c->V * c->p.nlat;
+    if (n_doubles != need) return fail(SU3_EINVAL, "n_doubles must be 72*V*nlat = " + std::to_string(need));
+    const Geom &g = c->g;
+    const size_t bytes = link_bytes_of(&c->p, g);
+    std::vector<unsigned char> buf;
+    try {
+        buf.assign(bytes, 0);
+    } catch (...) {
+        return fail(SU3_EINVAL, "out of host memory for the staging copy");
+    }
+    const long long nelem = (long long)g.nlat * g.Vh;
+    for (int par = 0; par < 2; ++par)
+        for (long long n = 0; n < nelem; ++n) {
+            long long site;
+            site_of_elem(g, par, n, &site);
+            for (int dir = 0; dir < 4; ++dir) {
+                const double *src = host + (size_t)(4 * site + dir) * 18;
+                for (int el = 0; el < 9; ++el) {
+                    const size_t idx = (size_t)((dir * 2 + par) * 9 + el) * (size_t)g.stride + (size_t)n;
+                    if (c->p.precision == 64) {
+                        double *v = (double *)buf.data() + 2 * idx;
+                        v[0] = src[2 * el];
+                        v[1] = src[2 * el + 1];
+                    } else {
+                        float *v = (float *)buf.data() + 2 * idx;
+                        v[0] = (float)src[2 * el];
+                        v[1] = (float)src[2 * el + 1];
+                    }
+                }
+            }
+        }
+    hipError_t e = hipMemcpyAsync(c->links, buf.data(), bytes, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "link copy");
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "link copy sync");
+    if (!c->started) {
+        e = su3hb::launch_zero_u64(counters_of(c), 2, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "counter reset");
+    }
+    c->started = true;
+    return SU3_OK;
+}
+
+su3_status su3_get_link_sample(su3_ctx *c, const uint64_t *lids, size_t n, double *host)
+{
+    su3_status st = check_ctx(c);
+    if (st != SU3_OK) return st;
+    if (n == 0) return SU3_OK;
+    if (!lids || !host) return fail(SU3_EINVAL, "lids and host must not be NULL");
+    st = check_started(c);
+    if (st != SU3_OK) return st;
+    const Geom &g = c->g;
+    const uint64_t nlinks = 4ull * c->V * (uint64_t)c->p.nlat;
+    const size_t esz = c->p.precision == 64 ? 16 : 8;
+    std::vector<unsigned char> buf;
+    try {
+        buf.resize(n * 9 * esz);
+    } catch (...) {
+        return fail(SU3_EINVAL, "out of host memory for the sample");
+    }
+    for (size_t k = 0; k < n; ++k) {
+        if (lids[k] >= nlinks) return fail(SU3_EINVAL, "link id " + std::to_string(lids[k]) + " out of range");
+        const uint64_t site = lids[k] / 4;
+        const int dir = (int)(lids[k] % 4);
+        const int layer = (int)(site / c->V);
+        uint64_t lex = site % c->V;
+        int x[4];
+        for (int mu = 0; mu < 4; ++mu) {
+            x[mu] = (int)(lex % (uint64_t)g.L[mu]);
+            lex /= (uint64_t)g.L[mu];
+        }
+        const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
+        const size_t elem = (size_t)layer * (size_t)g.Vh + (size_t)((site % c->V) >> 1);
+        for (int el = 0; el < 9; ++el) {
+            const size_t idx = (size_t)((dir * 2 + par) * 9 + el) * (size_t)g.stride + elem;
+            hipError_t e = hipMemcpyAsync(buf.data() + (k * 9 + el) * esz, (const unsigned char *)c->links + idx * esz,
+                                          esz, hipMemcpyDeviceToHost, c->stream);
+            if (e != hipSuccess) return hip_fail(e, "sample copy");
+        }
+    }
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "sample sync");
+    for (size_t k = 0; k < n * 9; ++k) {
+        if (c->p.precision == 64) {
+            host[2 * k] = ((const double *)buf.data())[2 * k];
+            host[2 * k + 1] = ((const double *)buf.data())[2 * k + 1];
+        } else {
+            host[2 * k] = (double)((const float *)buf.data())[2 * k];
+            host[2 * k + 1] = (double)((const float *)buf.data())[2 * k + 1];
+        }
+    }
+    return SU3_OK;
+}
+
+su3_status su3_get_sweep_index(su3_ctx *c, uint64_t *sweep_index)
+{
+    su3_status st = check_ctx(c);
+    if (st != SU3_OK) return st;
+    if (!sweep_index) return fail(SU3_EINVAL, "sweep_index is NULL");
+    *sweep_index = c->sweep_index;
+    return SU3_OK;
+}
+
+su3_status su3_set_sweep_index(su3_ctx *c, uint64_t sweep_index)
+{
+    su3_status st = check_ctx(c);
+    if (st != SU3_OK) return st;
+    c->sweep_index = sweep_index;
+    return SU3_OK;
+}
+
+su3_status su3_counters(su3_ctx *c, uint64_t *sweeps, uint64_t *kp_attempts, uint64_t *kp_accepts)
+{
+    su3_status st = check_ctx(c);
+    if (st != SU3_OK) return st;
+    st = check_started(c);
+    if (st != SU3_OK) return st;
+    unsigned long long h[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(h, counters_of(c), sizeof h, hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "counter copy");
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "counter sync");
+    if (sweeps) *sweeps = c->sweeps_done;
+    if (kp_attempts) *kp_attempts = h[0];
+    if (kp_accepts) *kp_accepts = h[1];
+    return SU3_OK;
+}
+
+su3_status su3_profile(su3_ctx *c, int32_t enable)
+{
+    su3_status st = check_ctx(c);
+    if (st != SU3_OK) return st;
+    c->profile = enable != 0;
+    return SU3_OK;
+}
+
+su3_status su3_profile_read(su3_ctx *c, double *total_ms, uint64_t *passes)
+{
+    su3_status st = check_ctx(c);
+    if (st != SU3_OK) return st;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "profile sync");
+    double tot = 0.0;
+    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (passes) *passes = c->ev_used / 2;
+    c->ev_used = 0;
+    return SU3_OK;
+}
+
+su3_status su3_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream)
+{
+    if (!dst || !src) return fail(SU3_EINVAL, "dst and src must not be NULL");
+    if (bytes % 16) return fail(SU3_EINVAL, "bytes must be a multiple of 16");
+    if (((uintptr_t)dst & 15u) || ((uintptr_t)src & 15u)) return fail(SU3_EINVAL, "buffers must be 16-byte aligned");
+    if (bytes == 0) return SU3_OK;
+    hipError_t e = su3hb::launch_copy(dst, src, bytes, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "copy kernel");
+    return SU3_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,311 @@
+// device.h -- device-side building blocks of the gfx950 heat-bath kernels:
+// complex 3x3 algebra, Philox4x64-10, uniform mapping, lattice indexing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace su3hb {
+
+// ---------------------------------------------------------------------------
+// storage types: one complex link entry per element of a component plane
+// ---------------------------------------------------------------------------
+template <typename R> struct Store;
+template <> struct Store<double> { using type = double2; };
+template <> struct Store<float> { using type = float2; };
+template <typename R> using store_t = typename Store<R>::type;
+
+template <typename R> struct Cx {
+    R re, im;
+};
+
+template <typename R> __device__ __forceinline__ Cx<R> cx(R re, R im) { return Cx<R>{re, im}; }
+
+// a * b
+template <typename R> __device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b)
+{
+    return Cx<R>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// c + a * b
+template <typename R> __device__ __forceinline__ Cx<R> cmadd(Cx<R> c, Cx<R> a, Cx<R> b)
+{
+    return Cx<R>{c.re + a.re * b.re - a.im * b.im, c.im + a.re * b.im + a.im * b.re};
+}
+// c + a * conj(b)
+template <typename R> __device__ __forceinline__ Cx<R> cmadd_nc(Cx<R> c, Cx<R> a, Cx<R> b)
+{
+    return Cx<R>{c.re + a.re * b.re + a.im * b.im, c.im + a.im * b.re - a.re * b.im};
+}
+// c + conj(a) * b
+template <typename R> __device__ __forceinline__ Cx<R> cmadd_cn(Cx<R> c, Cx<R> a, Cx<R> b)
+{
+    return Cx<R>{c.re + a.re * b.re + a.im * b.im, c.im + a.re * b.im - a.im * b.re};
+}
+
+template <typename R> struct M3 {
+    Cx<R> e[3][3];
+};
+
+// C += A B
+template <typename R> __device__ __forceinline__ void acc_nn(M3<R> &C, const M3<R> &A, const M3<R> &B)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) C.e[a][b] = cmadd(C.e[a][b], A.e[a][k], B.e[k][b]);
+}
+// C += A B^+
+template <typename R> __device__ __forceinline__ void acc_nd(M3<R> &C, const M3<R> &A, const M3<R> &B)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) C.e[a][b] = cmadd_nc(C.e[a][b], A.e[a][k], B.e[b][k]);
+}
+// C += A^+ B
+template <typename R> __device__ __forceinline__ void acc_dn(M3<R> &C, const M3<R> &A, const M3<R> &B)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) C.e[a][b] = cmadd_cn(C.e[a][b], A.e[k][a], B.e[k][b]);
+}
+
+template <typename R> __device__ __forceinline__ void set_zero(M3<R> &C)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) C.e[a][b] = Cx<R>{R(0), R(0)};
+}
+
+template <typename R> __device__ __forceinline__ M3<R> mul_nn(const M3<R> &A, const M3<R> &B)
+{
+    M3<R> C;
+    set_zero(C);
+    acc_nn(C, A, B);
+    return C;
+}
+
+template <typename R> __device__ __forceinline__ R retrace(const M3<R> &A)
+{
+    return A.e[0][0].re + A.e[1][1].re + A.e[2][2].re;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11)
+// ---------------------------------------------------------------------------
+struct U64x4 {
+    uint64_t w[4];
+};
+
+__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                                               uint64_t k1)
+{
+    constexpr uint64_t kMul0 = 0xD2E7470EE14C6C93ull, kMul1 = 0xCA5A826395121157ull;
+    constexpr uint64_t kBump0 = 0x9E3779B97F4A7C15ull, kBump1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t lo_a = kMul0 * c0, hi_a = __umul64hi(kMul0, c0);
+        const uint64_t lo_b = kMul1 * c2, hi_b = __umul64hi(kMul1, c2);
+        c0 = hi_b ^ c1 ^ k0;
+        c1 = lo_b;
+        c2 = hi_a ^ c3 ^ k1;
+        c3 = lo_a;
+        k0 += kBump0;
+        k1 += kBump1;
+    }
+    return U64x4{{c0, c1, c2, c3}};
+}
+
+// Purpose tags (counter word 3).
+enum : uint64_t { kTagHeatbath = 0, kTagHot = 1, kTagGauge = 2 };
+
+// (k + 1/2) * 2^-52 from the top 52 bits: exact in FP64, never 0 or 1.
+__device__ __forceinline__ double unif52(uint64_t w) { return (double(w >> 12) + 0.5) * 0x1p-52; }
+// (h + 1/2) * 2^-32 from a 32-bit half: exact in FP64, never 0 or 1.
+__device__ __forceinline__ double unif32(uint32_t h) { return (double(h) + 0.5) * 0x1p-32; }
+
+// ---------------------------------------------------------------------------
+// lattice geometry
+// ---------------------------------------------------------------------------
+// Sites are addressed by (layer, parity, i): i = lex >> 1 with
+// lex = x0 + L0 (x1 + L1 (x2 + L2 x3)); with L0 even, the two sites sharing
+// lex >> 1 have opposite parity.  Within a component plane the element of
+// site (layer, parity, i) is n = layer * Vh + i.
+struct Geom {
+    int L[4];
+    int Vh;             // V / 2
+    int nlat;
+    unsigned flip;      // layer-switch mask, 0 on a single torus
+    long long stride;   // elements per component plane (>= nlat * Vh, multiple of 64)
+};
+
+// Coordinates of the site with parity `par` and half-index i.
+__device__ __forceinline__ void site_coords(const Geom &g, int par, int i, int x[4])
+{
+    const int l0h = g.L[0] >> 1;
+    int r = i / l0h;
+    const int x0h = i - r * l0h;
+    int q = r / g.L[1];
+    x[1] = r - q * g.L[1];
+    r = q;
+    q = r / g.L[2];
+    x[2] = r - q * g.L[2];
+    x[3] = q;
+    x[0] = 2 * x0h + ((par + x[1] + x[2] + x[3]) & 1);
+}
+
+// Step coordinate D by S (+1 / -1) with periodic wrap; crossing the boundary
+// of a direction whose flip bit is set switches the layer.
+template <int D, int S> __device__ __forceinline__ void step(const Geom &g, int y[4], int &layer)
+{
+    if (S > 0) {
+        if (y[D] == g.L[D] - 1) {
+            y[D] = 0;
+            layer ^= (g.flip >> D) & 1;
+        } else {
+            y[D] += 1;
+        }
+    } else if (S < 0) {
+        if (y[D] == 0) {
+            y[D] = g.L[D] - 1;
+            layer ^= (g.flip >> D) & 1;
+        } else {
+            y[D] -= 1;
+        }
+    }
+}
+
+__device__ __forceinline__ int lex_of(const Geom &g, const int y[4])
+{
+    return y[0] + g.L[0] * (y[1] + g.L[1] * (y[2] + g.L[2] * y[3]));
+}
+
+// Plane element of the site x + SA*A + SB*B.
+template <int A, int SA, int B, int SB>
+__device__ __forceinline__ int nbr_elem(const Geom &g, const int x[4], int layer)
+{
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    int ly = layer;
+    step<A, SA>(g, y, ly);
+    step<B, SB>(g, y, ly);
+    return ly * g.Vh + (lex_of(g, y) >> 1);
+}
+
+// Base of the 9 planes of (direction, parity).
+template <typename R>
+__device__ __forceinline__ const store_t<R> *planes(const store_t<R> *links, const Geom &g, int dir, int par)
+{
+    return links + (size_t)((dir * 2 + par) * 9) * (size_t)g.stride;
+}
+template <typename R> __device__ __forceinline__ store_t<R> *planes(store_t<R> *links, const Geom &g, int dir, int par)
+{
+    return links + (size_t)((dir * 2 + par) * 9) * (size_t)g.stride;
+}
+
+template <typename R> __device__ __forceinline__ M3<R> load_link(const store_t<R> *base, long long stride, int n)
+{
+    M3<R> m;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        const store_t<R> v = base[(size_t)e * (size_t)stride + n];
+        m.e[e / 3][e % 3] = Cx<R>{v.x, v.y};
+    }
+    return m;
+}
+
+template <typename R> __device__ __forceinline__ void store_link(store_t<R> *base, long long stride, int n, const M3<R> &m)
+{
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        store_t<R> v;
+        v.x = m.e[e / 3][e % 3].re;
+        v.y = m.e[e / 3][e % 3].im;
+        base[(size_t)e * (size_t)stride + n] = v;
+    }
+}
+
+template <typename To, typename From> __device__ __forceinline__ M3<To> convert(const M3<From> &a)
+{
+    M3<To> b;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) b.e[r][c] = Cx<To>{To(a.e[r][c].re), To(a.e[r][c].im)};
+    return b;
+}
+
+// Reunitarisation in FP64: normalise row 0, orthogonalise and normalise row 1,
+// row 2 = conj(row0 x row1).
+__device__ __forceinline__ void reunit(M3<double> &u)
+{
+    Cx<double> *r0 = u.e[0], *r1 = u.e[1], *r2 = u.e[2];
+    const double n0 = sqrt(r0[0].re * r0[0].re + r0[0].im * r0[0].im + r0[1].re * r0[1].re + r0[1].im * r0[1].im +
+                           r0[2].re * r0[2].re + r0[2].im * r0[2].im);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        r0[k].re /= n0;
+        r0[k].im /= n0;
+    }
+    Cx<double> d{0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d = cmadd_cn(d, r0[k], r1[k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        r1[k].re -= d.re * r0[k].re - d.im * r0[k].im;
+        r1[k].im -= d.re * r0[k].im + d.im * r0[k].re;
+    }
+    const double n1 = sqrt(r1[0].re * r1[0].re + r1[0].im * r1[0].im + r1[1].re * r1[1].re + r1[1].im * r1[1].im +
+                           r1[2].re * r1[2].re + r1[2].im * r1[2].im);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        r1[k].re /= n1;
+        r1[k].im /= n1;
+    }
+    // r2_k = conj(r0_{k+1} r1_{k+2} - r0_{k+2} r1_{k+1})
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int a = (k + 1) % 3, b = (k + 2) % 3;
+        const Cx<double> p = cmul(r0[a], r1[b]), q = cmul(r0[b], r1[a]);
+        r2[k] = Cx<double>{p.re - q.re, -(p.im - q.im)};
+    }
+}
+
+// Haar-random SU(3) element keyed by (seed; id, 0, draw, tag): 12 normals by
+// Box-Muller from three Philox blocks, two complex Gaussian rows, reunit.
+__device__ __forceinline__ M3<double> haar_element(uint64_t seed, uint64_t id, uint64_t tag)
+{
+    constexpr double kTwoPi = 6.283185307179586476925286766559;
+    double gauss[12];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const U64x4 w = philox4x64_10(id, 0, (uint64_t)d, tag, seed, 0);
+#pragma unroll
+        for (int pr = 0; pr < 2; ++pr) {
+            const double ua = unif52(w.w[2 * pr]), ub = unif52(w.w[2 * pr + 1]);
+            const double rad = sqrt(-2.0 * log(ua));
+            double s, c;
+            sincos(kTwoPi * ub, &s, &c);
+            gauss[4 * d + 2 * pr] = rad * c;
+            gauss[4 * d + 2 * pr + 1] = rad * s;
+        }
+    }
+    M3<double> u;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        u.e[0][k] = Cx<double>{gauss[2 * k], gauss[2 * k + 1]};
+        u.e[1][k] = Cx<double>{gauss[6 + 2 * k], gauss[7 + 2 * k]};
+        u.e[2][k] = Cx<double>{0.0, 0.0};
+    }
+    reunit(u);
+    return u;
+}
+
+}  // namespace su3hb

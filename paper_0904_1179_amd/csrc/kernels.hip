@@ -1,0 +1,427 @@
+// kernels.hip -- gfx950 kernels of the checkerboard SU(3) heat bath.
+//
+// Link storage (structure of arrays): 72 component planes, plane index
+// (dir * 2 + parity) * 9 + (3 * row + col), each plane `stride` complex
+// numbers (double2 or float2); the link U_dir(x) of site x = (layer, parity, i)
+// is element n = layer * Vh + i of its 9 planes.  A wave of 64 consecutive
+// links therefore reads 64 consecutive complex numbers per plane (1 KiB in
+// FP64): every global access is a fully coalesced 16-byte (8-byte) vector load.
+//
+// The hot kernel is k_update<MU, R>: one checkerboard pass, i.e. every link
+// U_MU(x) with parity(x) = par, one thread per link.  It gathers the 18
+// neighbour links of the six staples (Wilson action), runs the
+// Cabibbo-Marinari heat bath on the SU(2) subgroups (0,1), (1,2), (0,2) with
+// Kennedy-Pendleton sampling, reunitarises in FP64 and writes the link back.
+// Links of one pass share no plaquette, so threads never read what another
+// thread of the same pass writes.
+#include "launch.h"
+
+namespace su3hb {
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// ---------------------------------------------------------------------------
+// staple: A += U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+ + U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)
+// written as a (c b)^+ + (e d)^+ f with
+//   a = U_nu(x+mu), b = U_mu(x+nu), c = U_nu(x), d = U_nu(x+mu-nu), e = U_mu(x-nu), f = U_nu(x-nu)
+// ---------------------------------------------------------------------------
+template <int MU, int NU, typename R>
+__device__ __forceinline__ void add_staple(M3<R> &A, const store_t<R> *__restrict__ links, const Geom &g,
+                                           const int x[4], int layer, int par, int n)
+{
+    if constexpr (NU != MU) {
+        const int opp = par ^ 1;
+        {
+            const M3<R> b = load_link<R>(planes<R>(links, g, MU, opp), g.stride, nbr_elem<NU, +1, MU, 0>(g, x, layer));
+            const M3<R> c = load_link<R>(planes<R>(links, g, NU, par), g.stride, n);
+            const M3<R> cb = mul_nn(c, b);
+            const M3<R> a = load_link<R>(planes<R>(links, g, NU, opp), g.stride, nbr_elem<MU, +1, NU, 0>(g, x, layer));
+            acc_nd(A, a, cb);
+        }
+        {
+            const M3<R> e = load_link<R>(planes<R>(links, g, MU, opp), g.stride, nbr_elem<NU, -1, MU, 0>(g, x, layer));
+            const M3<R> d = load_link<R>(planes<R>(links, g, NU, par), g.stride, nbr_elem<MU, +1, NU, -1>(g, x, layer));
+            const M3<R> ed = mul_nn(e, d);
+            const M3<R> f = load_link<R>(planes<R>(links, g, NU, opp), g.stride, nbr_elem<NU, -1, MU, 0>(g, x, layer));
+            acc_dn(A, ed, f);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Cabibbo-Marinari heat bath of one link in staple A.  W = U A; for subgroup
+// (i,j): v = 1/2 (Re(w_ii + w_jj), -Im(w_ij + w_ji), Re(w_ji - w_ij),
+// Im(w_jj - w_ii)), k = |v|, alpha = 2 beta k / 3.  Kennedy-Pendleton attempt t
+// uses Philox block (lid, sweep, sub<<32 | t, heat-bath tag):
+//   lambda^2 = -(ln u1 + cos^2(2 pi u2) ln u3) / (2 alpha), accept iff u4^2 <= 1 - lambda^2,
+//   a0 = 1 - 2 lambda^2, cos(theta) = 2 u5 - 1, phi = 2 pi u6;
+// then rows i, j of U and W are multiplied from the left by r = P(a) P(v/k)
+// with P(p) = [[p0 + i p3, p2 + i p1], [-p2 + i p1, p0 - i p3]].
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void heatbath(M3<R> &U, const M3<R> &A, double beta, uint64_t seed, uint64_t lid,
+                                         uint64_t sweep, int nhit, int &att, int &acc)
+{
+    M3<R> W = mul_nn(U, A);
+#pragma unroll
+    for (int sub = 0; sub < 3; ++sub) {
+        const int i = (sub == 1) ? 1 : 0;
+        const int j = (sub == 0) ? 1 : 2;
+        const double v0 = 0.5 * (double(W.e[i][i].re) + double(W.e[j][j].re));
+        const double v1 = -0.5 * (double(W.e[i][j].im) + double(W.e[j][i].im));
+        const double v2 = 0.5 * (double(W.e[j][i].re) - double(W.e[i][j].re));
+        const double v3 = 0.5 * (double(W.e[j][j].im) - double(W.e[i][i].im));
+        const double k = sqrt(v0 * v0 + v1 * v1 + v2 * v2 + v3 * v3);
+        if (k == 0.0) continue;
+        const double alpha = 2.0 * beta * k / 3.0;
+        bool ok = false;
+        double a0 = 1.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (int t = 0; t < nhit; ++t) {
+            const U64x4 w = philox4x64_10(lid, sweep, ((uint64_t)sub << 32) | (uint64_t)t, kTagHeatbath, seed, 0);
+            ++att;
+            const double u1 = unif52(w.w[0]);
+            const double u3 = unif52(w.w[1]);
+            const double u2 = unif32((uint32_t)w.w[2]);
+            const double u4 = unif32((uint32_t)(w.w[2] >> 32));
+            const double c = cos(kTwoPi * u2);
+            const double lam2 = -(log(u1) + c * c * log(u3)) / (2.0 * alpha);
+            if (u4 * u4 <= 1.0 - lam2) {
+                const double u5 = unif32((uint32_t)w.w[3]);
+                const double u6 = unif32((uint32_t)(w.w[3] >> 32));
+                a0 = 1.0 - 2.0 * lam2;
+                const double cth = 2.0 * u5 - 1.0;
+                const double sth = sqrt(1.0 - cth * cth);
+                double sph, cph;
+                sincos(kTwoPi * u6, &sph, &cph);
+                const double rho2 = 1.0 - a0 * a0;
+                const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
+                a1 = rho * sth * cph;
+                a2 = rho * sth * sph;
+                a3 = rho * cth;
+                ok = true;
+                break;
+            }
+        }
+        if (!ok) continue;
+        ++acc;
+        const double b0 = v0 / k, b1 = v1 / k, b2 = v2 / k, b3 = v3 / k;
+        // quaternion product c = a * b  <=>  P(c) = P(a) P(b)
+        const double c0 = a0 * b0 - a1 * b1 - a2 * b2 - a3 * b3;
+        const double c1 = a0 * b1 + b0 * a1 - (a2 * b3 - a3 * b2);
+        const double c2 = a0 * b2 + b0 * a2 - (a3 * b1 - a1 * b3);
+        const double c3 = a0 * b3 + b0 * a3 - (a1 * b2 - a2 * b1);
+        const Cx<R> r00{R(c0), R(c3)}, r01{R(c2), R(c1)}, r10{R(-c2), R(c1)}, r11{R(c0), R(-c3)};
+#pragma unroll
+        for (int col = 0; col < 3; ++col) {
+            const Cx<R> ui = U.e[i][col], uj = U.e[j][col];
+            U.e[i][col] = cmadd(cmul(r00, ui), r01, uj);
+            U.e[j][col] = cmadd(cmul(r10, ui), r11, uj);
+            const Cx<R> wi = W.e[i][col], wj = W.e[j][col];
+            W.e[i][col] = cmadd(cmul(r00, wi), r01, wj);
+            W.e[j][col] = cmadd(cmul(r10, wi), r11, wj);
+        }
+    }
+    M3<double> Ud = convert<double>(U);
+    reunit(Ud);
+    U = convert<R>(Ud);
+}
+
+template <int MU, typename R>
+__global__ __launch_bounds__(kBlock) void k_update(store_t<R> *__restrict__ links, const Geom g, const int par,
+                                                   const double beta, const uint64_t sweep, const uint64_t seed,
+                                                   const int nhit, unsigned long long *__restrict__ counters)
+{
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    int att = 0, acc = 0;
+    if (n < g.nlat * g.Vh) {
+        const int layer = n >= g.Vh ? 1 : 0;
+        const int i = n - layer * g.Vh;
+        int x[4];
+        site_coords(g, par, i, x);
+        M3<R> A;
+        set_zero(A);
+        add_staple<MU, 0, R>(A, links, g, x, layer, par, n);
+        add_staple<MU, 1, R>(A, links, g, x, layer, par, n);
+        add_staple<MU, 2, R>(A, links, g, x, layer, par, n);
+        add_staple<MU, 3, R>(A, links, g, x, layer, par, n);
+        store_t<R> *own = planes<R>(links, g, MU, par);
+        M3<R> U = load_link<R>(own, g.stride, n);
+        const uint64_t site = (uint64_t)layer * (uint64_t)(2 * g.Vh) + (uint64_t)lex_of(g, x);
+        heatbath<R>(U, A, beta, seed, 4 * site + MU, sweep, nhit, att, acc);
+        store_link<R>(own, g.stride, n, U);
+    }
+    // exact integer counts: wave sum of packed (attempts | accepts << 16), one atomic per wave
+    unsigned packed = (unsigned)att | ((unsigned)acc << 16);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) packed += __shfl_xor(packed, off);
+    if ((threadIdx.x & 63) == 0 && packed != 0) {
+        atomicAdd(&counters[0], (unsigned long long)(packed & 0xffffu));
+        atomicAdd(&counters[1], (unsigned long long)(packed >> 16));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// start configurations, reunitarisation, gauge transformation: one thread per
+// link; blockIdx.y = dir * 2 + parity
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool link_of_thread(const Geom &g, int &n, int &dir, int &par, int &layer, int x[4])
+{
+    n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.nlat * g.Vh) return false;
+    dir = blockIdx.y >> 1;
+    par = blockIdx.y & 1;
+    layer = n >= g.Vh ? 1 : 0;
+    site_coords(g, par, n - layer * g.Vh, x);
+    return true;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_start(store_t<R> *__restrict__ links, const Geom g, const int hot,
+                                                  const uint64_t seed)
+{
+    int n, dir, par, layer, x[4];
+    if (!link_of_thread(g, n, dir, par, layer, x)) return;
+    M3<double> u;
+    if (hot) {
+        const uint64_t site = (uint64_t)layer * (uint64_t)(2 * g.Vh) + (uint64_t)lex_of(g, x);
+        u = haar_element(seed, 4 * site + dir, kTagHot);
+    } else {
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) u.e[r][c] = Cx<double>{r == c ? 1.0 : 0.0, 0.0};
+    }
+    store_link<R>(planes<R>(links, g, dir, par), g.stride, n, convert<R>(u));
+}
+
+template <typename R> __global__ __launch_bounds__(kBlock) void k_reunit(store_t<R> *__restrict__ links, const Geom g)
+{
+    int n, dir, par, layer, x[4];
+    if (!link_of_thread(g, n, dir, par, layer, x)) return;
+    store_t<R> *base = planes<R>(links, g, dir, par);
+    M3<double> u = convert<double>(load_link<R>(base, g.stride, n));
+    reunit(u);
+    store_link<R>(base, g.stride, n, convert<R>(u));
+}
+
+template <int D>
+__device__ __forceinline__ uint64_t forward_site(const Geom &g, const int x[4], int layer)
+{
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    int ly = layer;
+    step<D, +1>(g, y, ly);
+    return (uint64_t)ly * (uint64_t)(2 * g.Vh) + (uint64_t)lex_of(g, y);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_gauge(store_t<R> *__restrict__ links, const Geom g, const uint64_t gseed)
+{
+    int n, dir, par, layer, x[4];
+    if (!link_of_thread(g, n, dir, par, layer, x)) return;
+    const uint64_t site = (uint64_t)layer * (uint64_t)(2 * g.Vh) + (uint64_t)lex_of(g, x);
+    uint64_t fwd;
+    switch (dir) {
+    case 0: fwd = forward_site<0>(g, x, layer); break;
+    case 1: fwd = forward_site<1>(g, x, layer); break;
+    case 2: fwd = forward_site<2>(g, x, layer); break;
+    default: fwd = forward_site<3>(g, x, layer); break;
+    }
+    const M3<double> gx = haar_element(gseed, site, kTagGauge);
+    const M3<double> gy = haar_element(gseed, fwd, kTagGauge);
+    store_t<R> *base = planes<R>(links, g, dir, par);
+    const M3<double> u = convert<double>(load_link<R>(base, g.stride, n));
+    const M3<double> t = mul_nn(gx, u);
+    M3<double> out;
+    set_zero(out);
+    acc_nd(out, t, gy);
+    store_link<R>(base, g.stride, n, convert<R>(out));
+}
+
+// ---------------------------------------------------------------------------
+// plaquette: sum over sites of Re Tr U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
+// = Re Tr P Q^+ with P = U_mu(x) U_nu(x+mu), Q = U_nu(x) U_mu(x+nu), in FP64.
+// Grid (nblk, nlat); fixed per-thread order, wave shuffles and a fixed
+// per-block order, so the sum is bitwise reproducible.
+// ---------------------------------------------------------------------------
+template <int MU, int NU, typename R>
+__device__ __forceinline__ double plaq_plane(const store_t<R> *__restrict__ links, const Geom &g, const int x[4],
+                                             int layer, int par, int n)
+{
+    const int opp = par ^ 1;
+    const M3<double> umu = convert<double>(load_link<R>(planes<R>(links, g, MU, par), g.stride, n));
+    const M3<double> unu_xmu =
+        convert<double>(load_link<R>(planes<R>(links, g, NU, opp), g.stride, nbr_elem<MU, +1, NU, 0>(g, x, layer)));
+    const M3<double> unu = convert<double>(load_link<R>(planes<R>(links, g, NU, par), g.stride, n));
+    const M3<double> umu_xnu =
+        convert<double>(load_link<R>(planes<R>(links, g, MU, opp), g.stride, nbr_elem<NU, +1, MU, 0>(g, x, layer)));
+    const M3<double> P = mul_nn(umu, unu_xmu);
+    const M3<double> Q = mul_nn(unu, umu_xnu);
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) s += P.e[a][b].re * Q.e[a][b].re + P.e[a][b].im * Q.e[a][b].im;
+    return s;
+}
+
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double wsum[kBlock / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kBlock / 64; ++w) s += wsum[w];
+    return s;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_plaq_partial(const store_t<R> *__restrict__ links, const Geom g,
+                                                         double *__restrict__ partials)
+{
+    const int layer = blockIdx.y;
+    double s = 0.0;
+    for (int t = blockIdx.x * kBlock + threadIdx.x; t < 2 * g.Vh; t += gridDim.x * kBlock) {
+        const int par = t >= g.Vh ? 1 : 0;
+        const int i = t - par * g.Vh;
+        int x[4];
+        site_coords(g, par, i, x);
+        const int n = layer * g.Vh + i;
+        s += plaq_plane<0, 1, R>(links, g, x, layer, par, n);
+        s += plaq_plane<0, 2, R>(links, g, x, layer, par, n);
+        s += plaq_plane<0, 3, R>(links, g, x, layer, par, n);
+        s += plaq_plane<1, 2, R>(links, g, x, layer, par, n);
+        s += plaq_plane<1, 3, R>(links, g, x, layer, par, n);
+        s += plaq_plane<2, 3, R>(links, g, x, layer, par, n);
+    }
+    const double b = block_sum(s);
+    if (threadIdx.x == 0) partials[layer * gridDim.x + blockIdx.x] = b;
+}
+
+// sums[1 + l] = sum over the partials of layer l; sums[0] = sum over layers
+__global__ __launch_bounds__(kBlock) void k_plaq_final(const double *__restrict__ partials, int nblk, int nlat,
+                                                       double *__restrict__ sums)
+{
+    double tot = 0.0;
+    for (int l = 0; l < nlat; ++l) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kBlock) s += partials[l * nblk + b];
+        const double r = block_sum(s);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            sums[1 + l] = r;
+            tot += r;
+        }
+    }
+    if (threadIdx.x == 0) sums[0] = tot;
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// bandwidth probe: 16-byte loads and stores, grid-stride
+__global__ __launch_bounds__(kBlock) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n)
+{
+    const size_t step = (size_t)gridDim.x * kBlock;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += step) dst[i] = src[i];
+}
+
+inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+int plaq_blocks(const Geom &g)
+{
+    const long long need = (2LL * g.Vh + kBlock - 1) / kBlock;
+    return (int)(need < kPlaqBlocksMax ? need : kPlaqBlocksMax);
+}
+
+hipError_t launch_start(int precision, void *links, const Geom &g, int hot, uint64_t seed, hipStream_t s)
+{
+    const dim3 grid(blocks_for((long long)g.nlat * g.Vh), 8);
+    if (precision == 64)
+        k_start<double><<<grid, kBlock, 0, s>>>((double2 *)links, g, hot, seed);
+    else
+        k_start<float><<<grid, kBlock, 0, s>>>((float2 *)links, g, hot, seed);
+    return hipGetLastError();
+}
+
+template <typename R>
+static void update_dispatch(store_t<R> *links, const Geom &g, int mu, int par, double beta, uint64_t sweep,
+                            uint64_t seed, int nhit, unsigned long long *counters, hipStream_t s)
+{
+    const dim3 grid(blocks_for((long long)g.nlat * g.Vh));
+    switch (mu) {
+    case 0: k_update<0, R><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters); break;
+    case 1: k_update<1, R><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters); break;
+    case 2: k_update<2, R><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters); break;
+    default: k_update<3, R><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters); break;
+    }
+}
+
+hipError_t launch_update(int precision, void *links, const Geom &g, int mu, int par, double beta, uint64_t sweep,
+                         uint64_t seed, int nhit, unsigned long long *counters, hipStream_t s)
+{
+    if (precision == 64)
+        update_dispatch<double>((double2 *)links, g, mu, par, beta, sweep, seed, nhit, counters, s);
+    else
+        update_dispatch<float>((float2 *)links, g, mu, par, beta, sweep, seed, nhit, counters, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_plaquette(int precision, const void *links, const Geom &g, double *partials, double *sums,
+                            hipStream_t s)
+{
+    const int nblk = plaq_blocks(g);
+    const dim3 grid(nblk, g.nlat);
+    if (precision == 64)
+        k_plaq_partial<double><<<grid, kBlock, 0, s>>>((const double2 *)links, g, partials);
+    else
+        k_plaq_partial<float><<<grid, kBlock, 0, s>>>((const float2 *)links, g, partials);
+    k_plaq_final<<<1, kBlock, 0, s>>>(partials, nblk, g.nlat, sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_reunit(int precision, void *links, const Geom &g, hipStream_t s)
+{
+    const dim3 grid(blocks_for((long long)g.nlat * g.Vh), 8);
+    if (precision == 64)
+        k_reunit<double><<<grid, kBlock, 0, s>>>((double2 *)links, g);
+    else
+        k_reunit<float><<<grid, kBlock, 0, s>>>((float2 *)links, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauge(int precision, void *links, const Geom &g, uint64_t gseed, hipStream_t s)
+{
+    const dim3 grid(blocks_for((long long)g.nlat * g.Vh), 8);
+    if (precision == 64)
+        k_gauge<double><<<grid, kBlock, 0, s>>>((double2 *)links, g, gseed);
+    else
+        k_gauge<float><<<grid, kBlock, 0, s>>>((float2 *)links, g, gseed);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s)
+{
+    k_zero_u64<<<1, 64, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / 16;
+    long long want = (long long)((n + kBlock - 1) / kBlock);
+    const unsigned grid = (unsigned)(want < 8192 ? (want > 0 ? want : 1) : 8192);
+    k_copy<<<grid, kBlock, 0, s>>>((const uint4 *)src, (uint4 *)dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace su3hb

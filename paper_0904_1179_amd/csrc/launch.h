@@ -1,0 +1,26 @@
+// launch.h -- host-side launchers of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.h"
+
+namespace su3hb {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 waves of 64)
+constexpr int kPlaqBlocksMax = 2048; // workgroups per layer of the plaquette reduction
+
+int plaq_blocks(const Geom &g);
+
+hipError_t launch_start(int precision, void *links, const Geom &g, int hot, uint64_t seed, hipStream_t s);
+hipError_t launch_update(int precision, void *links, const Geom &g, int mu, int par, double beta, uint64_t sweep,
+                         uint64_t seed, int nhit, unsigned long long *counters, hipStream_t s);
+hipError_t launch_plaquette(int precision, const void *links, const Geom &g, double *partials, double *sums,
+                            hipStream_t s);
+hipError_t launch_reunit(int precision, void *links, const Geom &g, hipStream_t s);
+hipError_t launch_gauge(int precision, void *links, const Geom &g, uint64_t gseed, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+}  // namespace su3hb
