@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Throughput of the checkerboard SU(3) heat-bath sweep on one MI355X.
+
+Workload (default): a 32^4 periodic lattice, beta = 5.7, FP64 links, hot
+(Haar-random) start from Philox seed 1, 1-hit heat bath.  One step = one sweep
+(8 checkerboard passes, 4 * 32^4 link updates) followed by one plaquette
+measurement.  `value` is link updates per second over the timed steps, with
+the lattice already resident in HBM.  The start configuration is created
+before the timed region, as the paper excludes it from its timings (Sec. 2).
+
+Also reported on the same JSON line:
+  roofline      the heat-bath pass kernel against HBM bandwidth, timed with
+                HIP events around every pass launch on the library's stream
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
+  fp32          the FP32-link tier on the same workload and its plaquette
+                deviation from the FP64 chain
+  serving       the mixed job stream (p50/p99 latency), when --serving is given
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+LINK_BYTES = {64: 144, 32: 72}  # one SU(3) matrix, 18 reals
+TRANSFERS_PER_UPDATE = 9  # each pass reads all 4*V*nlat links and writes V*nlat/2 of them
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0904_1179_amd", "csrc", f) for f in ("kernels.hip", "device.h")]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(name):
+    """HBM bytes per launch measured with rocprofv3 counters, if taken on the current kernel source."""
+    path = os.path.join(PROFILE_DIR, name)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_gpu(L, precision, steps, warmup, beta, seed=1):
+    import torch
+
+    from paper_0904_1179_amd import Lattice
+
+    lat = Lattice(L, nlat=1, precision=precision, seed=seed)
+    lat.start(hot=True)
+    for _ in range(warmup):
+        lat.sweep(1, beta)
+        lat.plaquette()
+    torch.cuda.synchronize()
+    lat.profile(True)
+    lat.profile_read()
+    plaq = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        lat.sweep(1, beta)
+        plaq.append(float(lat.plaquette()[0]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pass_ms, passes = lat.profile_read()
+    lat.profile(False)
+    V = L ** 4
+    return {"seconds": t1 - t0, "updates": 4 * V * steps, "pass_ms": pass_ms / max(passes, 1), "passes": passes,
+            "plaquette": plaq, "lattice": lat}
+
+
+def copy_probe_gbs(nbytes=1 << 30, reps=10):
+    import torch
+
+    from paper_0904_1179_amd import su3_stream_copy
+
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    su3_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        su3_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def fp32_deviation(L, beta, sweeps=2, seed=1):
+    """Plaquette of the FP32 tier against the FP64 chain from the same start, per sweep."""
+    from paper_0904_1179_amd import Lattice
+
+    a = Lattice(L, precision=64, seed=seed)
+    b = Lattice(L, precision=32, seed=seed)
+    a.start(hot=True)
+    b.start(hot=True)
+    out = []
+    for _ in range(sweeps):
+        a.sweep(1, beta)
+        b.sweep(1, beta)
+        pa, pb = a.plaquette()[0], b.plaquette()[0]
+        out.append(abs(pb - pa) / abs(pa))
+    return out
+
+
+def cpu_baseline(L, beta, seed=1):
+    """The FP64 oracle, as it stands, on the host cores: one sweep of the same lattice."""
+    from oracle import su3ref
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    lat = su3ref.Oracle(L, nlat=1, seed=seed)
+    lat.start(True)
+    t0 = time.perf_counter()
+    lat.sweep(1, beta, nthreads=threads)
+    t = time.perf_counter() - t0
+    one = su3ref.Oracle(16, nlat=1, seed=seed)
+    one.start(True)
+    t1 = time.perf_counter()
+    one.sweep(1, beta, nthreads=1)
+    t_one = time.perf_counter() - t1
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": 4 * L ** 4 / t, "unit": "link updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 sweep of the {L}^4 hot-start lattice ({4 * L ** 4} link updates) at beta={beta}, "
+                      f"OpenMP over the links of each pass; start excluded",
+            "seconds": t, "host_cpu": cpu,
+            "single_core": {"value": 4 * 16 ** 4 / t_one, "us_per_update": t_one / (4 * 16 ** 4) * 1e6,
+                            "sample": "1 sweep of a 16^4 hot-start lattice, 1 thread"}}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--L", type=int, default=32)
+    ap.add_argument("--beta", type=float, default=5.7)
+    ap.add_argument("--precision", type=int, default=64, choices=(64, 32))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-copy-probe", action="store_true")
+    ap.add_argument("--serving", action="store_true", help="also run the mixed job stream")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        if int(os.environ.get("RANK", "0")) == 0:
+            print("bench.py: this build runs one lattice on one GPU; --gpus above 1 is not supported "
+                  "(independent chains or a halo-exchange decomposition would be needed)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    torch.cuda.set_device(0)
+    L, beta, prec = args.L, args.beta, args.precision
+    main_run = run_gpu(L, prec, args.steps, args.warmup, beta)
+    ups = main_run["updates"] / main_run["seconds"]
+    pass_s = main_run["pass_ms"] * 1e-3
+    links_per_pass = L ** 4 // 2
+    alg_bytes = TRANSFERS_PER_UPDATE * LINK_BYTES[prec] * links_per_pass
+    achieved = alg_bytes / pass_s / 1e9
+    traffic = stored_traffic(f"k_update_{L}x4_fp{prec}_traffic.txt")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": f"k_update<mu, {'double' if prec == 64 else 'float'}>",
+                "algorithmic_bytes_per_launch": alg_bytes, "launch_us": round(main_run["pass_ms"] * 1e3, 2),
+                "launches_timed": main_run["passes"]}
+    if not args.no_copy_probe:
+        roofline["copy_probe_gbs"] = round(copy_probe_gbs(), 1)
+    del main_run["lattice"]
+
+    out = {"metric": "SU(3) link updates/sec at 32^4 (FP64 checkerboard heat-bath sweep + plaquette)",
+           "value": ups, "unit": "link updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": main_run["seconds"] / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64" if prec == 64 else "f32",
+           "data": "synthetic (Haar-random hot start from Philox seed 1)",
+           "config": {"workload": f"{L}^4 periodic lattice, beta={beta}, hot start, 1-hit heat bath, "
+                                  f"step = 1 sweep + 1 plaquette", "L": L, "nlat": 1, "beta": beta,
+                      "precision": prec, "parallelism": "single GPU"},
+           "us_per_update_gpu": main_run["seconds"] / main_run["updates"] * 1e6,
+           "plaquette_last": main_run["plaquette"][-1],
+           "roofline": roofline}
+
+    if not args.no_fp32 and prec == 64:
+        r32 = run_gpu(L, 32, args.steps, args.warmup, beta)
+        del r32["lattice"]
+        v32 = r32["updates"] / r32["seconds"]
+        alg32 = TRANSFERS_PER_UPDATE * LINK_BYTES[32] * links_per_pass
+        out["fp32"] = {"value": v32, "unit": "link updates/s", "speedup_vs_fp64": v32 / ups,
+                       "launch_us": round(r32["pass_ms"] * 1e3, 2),
+                       "achieved_gbs": round(alg32 / (r32["pass_ms"] * 1e-3) / 1e9, 1),
+                       "plaquette_rel_err_vs_fp64_per_sweep": fp32_deviation(L, beta),
+                       "note": "FP32 links and products; FP64 heat-bath scalars, reunitarisation and sums"}
+
+    if args.serving:
+        from paper_0904_1179_amd.serve import run_stream_benchmark
+
+        out["serving"] = run_stream_benchmark()
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(L, beta)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -67,8 +67,9 @@ typedef struct {
 
 /* Device bytes the caller must provide for the links and the scratch area.
  * Links: 72 component planes (4 directions x 2 parities x 9 complex entries),
- * each of round_up(nlat*V/2, 64) complex numbers of the link precision.
- * Scratch: plaquette partial sums and heat-bath counters (a few hundred kB).
+ * each of round_up(nlat*V/2, 64) + 64 complex numbers of the link precision.
+ * Scratch: heat-bath counter slots (64 KiB) and plaquette partial sums (up
+ * to 64 KiB per layer).
  * SU3_EINVAL on invalid parameters. */
 su3_status su3_footprint(const su3_params *p, size_t *link_bytes, size_t *scratch_bytes);
 

@@ -51,11 +51,12 @@ su3_status hip_fail(hipError_t e, const char *where)
     return fail(SU3_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-// scratch layout (bytes): [0, 16) heat-bath counters (2 x u64);
-// [256, 256 + 8*(1+nlat)) plaquette sums; [512, ...) plaquette partials
+// scratch layout (bytes): [0, 16*kCounterSlots) heat-bath counter slots (pairs
+// of u64 attempts, accepts); then 256 bytes of plaquette sums; then the
+// plaquette partials
 constexpr size_t kOffCounters = 0;
-constexpr size_t kOffSums = 256;
-constexpr size_t kOffPartials = 512;
+constexpr size_t kOffSums = 16 * (size_t)su3hb::kCounterSlots;
+constexpr size_t kOffPartials = kOffSums + 256;
 
 long long round_up(long long a, long long m) { return (a + m - 1) / m * m; }
 
@@ -87,7 +88,15 @@ Geom make_geom(const su3_params *p)
     g.Vh = (int)(V / 2);
     g.nlat = p->nlat;
     g.flip = p->nlat == 2 ? p->flip_mask : 0u;
-    g.stride = round_up((long long)p->nlat * (V / 2), 64);
+    // +64: consecutive planes are offset by 64 elements (1 KiB in FP64) from a
+    // large power-of-two stride, so the 9 entries of a link do not all fall in
+    // the same L2 channel and set
+    g.stride = round_up((long long)p->nlat * (V / 2), 64) + 64;
+    // pass order: x2 cut into chunks of w2 planes, the largest divisor of L2
+    // not above L2/8 (one chunk per XCD when L2 is a multiple of 8)
+    g.w2 = 1;
+    for (int w = 1; w <= p->L[2] / 8; ++w)
+        if (p->L[2] % w == 0) g.w2 = w;
     return g;
 }
 
@@ -211,7 +220,7 @@ su3_status su3_start(su3_ctx *c, int32_t hot)
     if (hot != 0 && hot != 1) return fail(SU3_EINVAL, "hot must be 0 (cold) or 1 (hot)");
     hipError_t e = su3hb::launch_start(c->p.precision, c->links, c->g, hot, c->p.seed, c->stream);
     if (e != hipSuccess) return hip_fail(e, "start kernel");
-    e = su3hb::launch_zero_u64(counters_of(c), 2, c->stream);
+    e = su3hb::launch_zero_u64(counters_of(c), 2 * su3hb::kCounterSlots, c->stream);
     if (e != hipSuccess) return hip_fail(e, "counter reset");
     c->started = true;
     c->sweep_index = 0;
@@ -385,7 +394,7 @@ su3_status su3_set_links(su3_ctx *c, const double *host, size_t n_doubles)
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "link copy sync");
     if (!c->started) {
-        e = su3hb::launch_zero_u64(counters_of(c), 2, c->stream);
+        e = su3hb::launch_zero_u64(counters_of(c), 2 * su3hb::kCounterSlots, c->stream);
         if (e != hipSuccess) return hip_fail(e, "counter reset");
     }
     c->started = true;
@@ -466,14 +475,20 @@ su3_status su3_counters(su3_ctx *c, uint64_t *sweeps, uint64_t *kp_attempts, uin
     if (st != SU3_OK) return st;
     st = check_started(c);
     if (st != SU3_OK) return st;
-    unsigned long long h[2] = {0, 0};
-    hipError_t e = hipMemcpyAsync(h, counters_of(c), sizeof h, hipMemcpyDeviceToHost, c->stream);
+    std::vector<unsigned long long> h(2 * su3hb::kCounterSlots);
+    hipError_t e = hipMemcpyAsync(h.data(), counters_of(c), h.size() * sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, c->stream);
     if (e != hipSuccess) return hip_fail(e, "counter copy");
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "counter sync");
+    unsigned long long att = 0, acc = 0;
+    for (int k = 0; k < su3hb::kCounterSlots; ++k) {
+        att += h[2 * k];
+        acc += h[2 * k + 1];
+    }
     if (sweeps) *sweeps = c->sweeps_done;
-    if (kp_attempts) *kp_attempts = h[0];
-    if (kp_accepts) *kp_accepts = h[1];
+    if (kp_attempts) *kp_attempts = att;
+    if (kp_accepts) *kp_accepts = acc;
     return SU3_OK;
 }
 

@@ -133,6 +133,22 @@ __device__ __forceinline__ double unif52(uint64_t w) { return (double(w >> 12) +
 __device__ __forceinline__ double unif32(uint32_t h) { return (double(h) + 0.5) * 0x1p-32; }
 
 // ---------------------------------------------------------------------------
+// XCD-aware workgroup order.  MI355X deals workgroups round-robin to its 8
+// XCDs, each with a private L2: workgroup b runs on XCD b % 8.  Remapping b to
+// a logical tile index so that XCD k owns the contiguous range of tiles
+// [k * n/8, (k+1) * n/8) keeps neighbouring tiles, which share staple links,
+// on one L2.  A bijection for any n.
+// ---------------------------------------------------------------------------
+constexpr int kNumXcd = 8;
+
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int xcd = b % kNumXcd, local = b / kNumXcd;
+    const int per = n / kNumXcd, rem = n % kNumXcd;
+    return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+// ---------------------------------------------------------------------------
 // lattice geometry
 // ---------------------------------------------------------------------------
 // Sites are addressed by (layer, parity, i): i = lex >> 1 with
@@ -145,6 +161,7 @@ struct Geom {
     int nlat;
     unsigned flip;      // layer-switch mask, 0 on a single torus
     long long stride;   // elements per component plane (>= nlat * Vh, multiple of 64)
+    int w2;             // chunk width of the pass order (divides L2)
 };
 
 // Coordinates of the site with parity `par` and half-index i.
@@ -162,21 +179,22 @@ __device__ __forceinline__ void site_coords(const Geom &g, int par, int i, int x
     x[0] = 2 * x0h + ((par + x[1] + x[2] + x[3]) & 1);
 }
 
-// Step coordinate D by S (+1 / -1) with periodic wrap; crossing the boundary
-// of a direction whose flip bit is set switches the layer.
-template <int D, int S> __device__ __forceinline__ void step(const Geom &g, int y[4], int &layer)
+// Step coordinate D by S (+1 / -1, 0 = no step) with periodic wrap; on a
+// double-layered torus (DLT = true) crossing the boundary of a direction whose
+// flip bit is set switches the layer.
+template <int D, int S, bool DLT = true> __device__ __forceinline__ void step(const Geom &g, int y[4], int &layer)
 {
     if (S > 0) {
         if (y[D] == g.L[D] - 1) {
             y[D] = 0;
-            layer ^= (g.flip >> D) & 1;
+            if (DLT) layer ^= (g.flip >> D) & 1;
         } else {
             y[D] += 1;
         }
     } else if (S < 0) {
         if (y[D] == 0) {
             y[D] = g.L[D] - 1;
-            layer ^= (g.flip >> D) & 1;
+            if (DLT) layer ^= (g.flip >> D) & 1;
         } else {
             y[D] -= 1;
         }
@@ -189,14 +207,39 @@ __device__ __forceinline__ int lex_of(const Geom &g, const int y[4])
 }
 
 // Plane element of the site x + SA*A + SB*B.
-template <int A, int SA, int B, int SB>
+template <int A, int SA, int B, int SB, bool DLT = true>
 __device__ __forceinline__ int nbr_elem(const Geom &g, const int x[4], int layer)
 {
     int y[4] = {x[0], x[1], x[2], x[3]};
     int ly = layer;
-    step<A, SA>(g, y, ly);
-    step<B, SB>(g, y, ly);
-    return ly * g.Vh + (lex_of(g, y) >> 1);
+    step<A, SA, DLT>(g, y, ly);
+    step<B, SB, DLT>(g, y, ly);
+    const int e = lex_of(g, y) >> 1;
+    return DLT ? ly * g.Vh + e : e;
+}
+
+// Processing order of one pass.  Thread v of a layer handles the site with
+// half-index i(v): v = x0h + (L0/2)(x1 + L1(x2' + w2 (x3 + L3 c))) with
+// x2 = c w2 + x2', i.e. the lattice is cut into L2/w2 chunks of w2 planes in
+// the x2 direction and each chunk is swept along x3.  Together with xcd_tile
+// each XCD owns whole chunks, so a link is re-read while it is still in that
+// XCD's L2.  Lanes of a wave still cover consecutive x0, so loads stay
+// coalesced.  w2 must divide L2.
+__device__ __forceinline__ int chunk_order(const Geom &g, int v, int w2)
+{
+    const int l0h = g.L[0] >> 1;
+    int r = v / l0h;
+    const int x0h = v - r * l0h;
+    int q = r / g.L[1];
+    const int x1 = r - q * g.L[1];
+    r = q;
+    q = r / w2;
+    const int x2p = r - q * w2;
+    r = q;
+    q = r / g.L[3];
+    const int x3 = r - q * g.L[3];
+    const int x2 = q * w2 + x2p;
+    return x0h + l0h * (x1 + g.L[1] * (x2 + g.L[2] * x3));
 }
 
 // Base of the 9 planes of (direction, parity).

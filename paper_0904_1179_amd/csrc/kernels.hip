@@ -27,24 +27,29 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 // written as a (c b)^+ + (e d)^+ f with
 //   a = U_nu(x+mu), b = U_mu(x+nu), c = U_nu(x), d = U_nu(x+mu-nu), e = U_mu(x-nu), f = U_nu(x-nu)
 // ---------------------------------------------------------------------------
-template <int MU, int NU, typename R>
+template <int MU, int NU, typename R, bool DLT>
 __device__ __forceinline__ void add_staple(M3<R> &A, const store_t<R> *__restrict__ links, const Geom &g,
                                            const int x[4], int layer, int par, int n)
 {
     if constexpr (NU != MU) {
         const int opp = par ^ 1;
         {
-            const M3<R> b = load_link<R>(planes<R>(links, g, MU, opp), g.stride, nbr_elem<NU, +1, MU, 0>(g, x, layer));
+            const M3<R> b =
+                load_link<R>(planes<R>(links, g, MU, opp), g.stride, nbr_elem<NU, +1, MU, 0, DLT>(g, x, layer));
             const M3<R> c = load_link<R>(planes<R>(links, g, NU, par), g.stride, n);
             const M3<R> cb = mul_nn(c, b);
-            const M3<R> a = load_link<R>(planes<R>(links, g, NU, opp), g.stride, nbr_elem<MU, +1, NU, 0>(g, x, layer));
+            const M3<R> a =
+                load_link<R>(planes<R>(links, g, NU, opp), g.stride, nbr_elem<MU, +1, NU, 0, DLT>(g, x, layer));
             acc_nd(A, a, cb);
         }
         {
-            const M3<R> e = load_link<R>(planes<R>(links, g, MU, opp), g.stride, nbr_elem<NU, -1, MU, 0>(g, x, layer));
-            const M3<R> d = load_link<R>(planes<R>(links, g, NU, par), g.stride, nbr_elem<MU, +1, NU, -1>(g, x, layer));
+            const M3<R> e =
+                load_link<R>(planes<R>(links, g, MU, opp), g.stride, nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer));
+            const M3<R> d =
+                load_link<R>(planes<R>(links, g, NU, par), g.stride, nbr_elem<MU, +1, NU, -1, DLT>(g, x, layer));
             const M3<R> ed = mul_nn(e, d);
-            const M3<R> f = load_link<R>(planes<R>(links, g, NU, opp), g.stride, nbr_elem<NU, -1, MU, 0>(g, x, layer));
+            const M3<R> f =
+                load_link<R>(planes<R>(links, g, NU, opp), g.stride, nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer));
             acc_dn(A, ed, f);
         }
     }
@@ -60,10 +65,11 @@ __device__ __forceinline__ void add_staple(M3<R> &A, const store_t<R> *__restric
 // then rows i, j of U and W are multiplied from the left by r = P(a) P(v/k)
 // with P(p) = [[p0 + i p3, p2 + i p1], [-p2 + i p1, p0 - i p3]].
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, bool HIT1>
 __device__ __forceinline__ void heatbath(M3<R> &U, const M3<R> &A, double beta, uint64_t seed, uint64_t lid,
                                          uint64_t sweep, int nhit, int &att, int &acc)
 {
+    if (HIT1) nhit = 1;  // 1-hit: a single attempt, no loop
     M3<R> W = mul_nn(U, A);
 #pragma unroll
     for (int sub = 0; sub < 3; ++sub) {
@@ -78,7 +84,7 @@ __device__ __forceinline__ void heatbath(M3<R> &U, const M3<R> &A, double beta, 
         const double alpha = 2.0 * beta * k / 3.0;
         bool ok = false;
         double a0 = 1.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        for (int t = 0; t < nhit; ++t) {
+        for (int t = 0; t < (HIT1 ? 1 : nhit); ++t) {
             const U64x4 w = philox4x64_10(lid, sweep, ((uint64_t)sub << 32) | (uint64_t)t, kTagHeatbath, seed, 0);
             ++att;
             const double u1 = unif52(w.w[0]);
@@ -128,37 +134,52 @@ __device__ __forceinline__ void heatbath(M3<R> &U, const M3<R> &A, double beta, 
     U = convert<R>(Ud);
 }
 
-template <int MU, typename R>
+template <int MU, typename R, bool HIT1, bool DLT>
 __global__ __launch_bounds__(kBlock) void k_update(store_t<R> *__restrict__ links, const Geom g, const int par,
                                                    const double beta, const uint64_t sweep, const uint64_t seed,
                                                    const int nhit, unsigned long long *__restrict__ counters)
 {
-    const int n = blockIdx.x * kBlock + threadIdx.x;
+    const int v = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     int att = 0, acc = 0;
-    if (n < g.nlat * g.Vh) {
-        const int layer = n >= g.Vh ? 1 : 0;
-        const int i = n - layer * g.Vh;
+    if (v < g.nlat * g.Vh) {
+        const int layer = DLT && v >= g.Vh ? 1 : 0;
+        const int i = chunk_order(g, v - layer * g.Vh, g.w2);
+        const int n = layer * g.Vh + i;
         int x[4];
         site_coords(g, par, i, x);
         M3<R> A;
         set_zero(A);
-        add_staple<MU, 0, R>(A, links, g, x, layer, par, n);
-        add_staple<MU, 1, R>(A, links, g, x, layer, par, n);
-        add_staple<MU, 2, R>(A, links, g, x, layer, par, n);
-        add_staple<MU, 3, R>(A, links, g, x, layer, par, n);
+        add_staple<MU, 0, R, DLT>(A, links, g, x, layer, par, n);
+        add_staple<MU, 1, R, DLT>(A, links, g, x, layer, par, n);
+        add_staple<MU, 2, R, DLT>(A, links, g, x, layer, par, n);
+        add_staple<MU, 3, R, DLT>(A, links, g, x, layer, par, n);
         store_t<R> *own = planes<R>(links, g, MU, par);
         M3<R> U = load_link<R>(own, g.stride, n);
         const uint64_t site = (uint64_t)layer * (uint64_t)(2 * g.Vh) + (uint64_t)lex_of(g, x);
-        heatbath<R>(U, A, beta, seed, 4 * site + MU, sweep, nhit, att, acc);
+        heatbath<R, HIT1>(U, A, beta, seed, 4 * site + MU, sweep, nhit, att, acc);
         store_link<R>(own, g.stride, n, U);
     }
-    // exact integer counts: wave sum of packed (attempts | accepts << 16), one atomic per wave
+    // exact integer counts: packed (attempts | accepts << 16) summed over the
+    // workgroup, then added to counter slot blockIdx % kCounterSlots, so no two
+    // concurrent workgroups update the same address
     unsigned packed = (unsigned)att | ((unsigned)acc << 16);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) packed += __shfl_xor(packed, off);
-    if ((threadIdx.x & 63) == 0 && packed != 0) {
-        atomicAdd(&counters[0], (unsigned long long)(packed & 0xffffu));
-        atomicAdd(&counters[1], (unsigned long long)(packed >> 16));
+    __shared__ unsigned wsum[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = packed;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = 0, b = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) {
+            a += wsum[w] & 0xffffu;
+            b += wsum[w] >> 16;
+        }
+        if (a != 0) {
+            unsigned long long *slot = counters + 2 * (blockIdx.x % kCounterSlots);
+            atomicAdd(&slot[0], a);
+            atomicAdd(&slot[1], b);
+        }
     }
 }
 
@@ -280,23 +301,34 @@ __device__ __forceinline__ double block_sum(double v)
 }
 
 template <typename R>
+__device__ __forceinline__ double plaq_site(const store_t<R> *__restrict__ links, const Geom &g, int layer, int par,
+                                           int i)
+{
+    int x[4];
+    site_coords(g, par, i, x);
+    const int n = layer * g.Vh + i;
+    double s = plaq_plane<0, 1, R>(links, g, x, layer, par, n);
+    s += plaq_plane<0, 2, R>(links, g, x, layer, par, n);
+    s += plaq_plane<0, 3, R>(links, g, x, layer, par, n);
+    s += plaq_plane<1, 2, R>(links, g, x, layer, par, n);
+    s += plaq_plane<1, 3, R>(links, g, x, layer, par, n);
+    s += plaq_plane<2, 3, R>(links, g, x, layer, par, n);
+    return s;
+}
+
+// Grid (nblk, nlat): thread i of a layer sums the plaquettes of both sites
+// with half-index i (x0 = 2*(i mod L0/2) and its x0 neighbour), so the links
+// of both parities around a tile are read while they are in L2.
+template <typename R>
 __global__ __launch_bounds__(kBlock) void k_plaq_partial(const store_t<R> *__restrict__ links, const Geom g,
                                                          double *__restrict__ partials)
 {
     const int layer = blockIdx.y;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     double s = 0.0;
-    for (int t = blockIdx.x * kBlock + threadIdx.x; t < 2 * g.Vh; t += gridDim.x * kBlock) {
-        const int par = t >= g.Vh ? 1 : 0;
-        const int i = t - par * g.Vh;
-        int x[4];
-        site_coords(g, par, i, x);
-        const int n = layer * g.Vh + i;
-        s += plaq_plane<0, 1, R>(links, g, x, layer, par, n);
-        s += plaq_plane<0, 2, R>(links, g, x, layer, par, n);
-        s += plaq_plane<0, 3, R>(links, g, x, layer, par, n);
-        s += plaq_plane<1, 2, R>(links, g, x, layer, par, n);
-        s += plaq_plane<1, 3, R>(links, g, x, layer, par, n);
-        s += plaq_plane<2, 3, R>(links, g, x, layer, par, n);
+    for (int i = tile * kBlock + threadIdx.x; i < g.Vh; i += gridDim.x * kBlock) {
+        s += plaq_site<R>(links, g, layer, 0, i);
+        s += plaq_site<R>(links, g, layer, 1, i);
     }
     const double b = block_sum(s);
     if (threadIdx.x == 0) partials[layer * gridDim.x + blockIdx.x] = b;
@@ -326,11 +358,19 @@ __global__ void k_zero_u64(unsigned long long *p, int n)
     if (i < n) p[i] = 0ull;
 }
 
-// bandwidth probe: 16-byte loads and stores, grid-stride
+// bandwidth probe: 16-byte loads and stores, four in flight per thread, grid-stride
 __global__ __launch_bounds__(kBlock) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n)
 {
     const size_t step = (size_t)gridDim.x * kBlock;
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += step) dst[i] = src[i];
+    size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; i + 3 * step < n; i += 4 * step) {
+        const uint4 a = src[i], b = src[i + step], c = src[i + 2 * step], d = src[i + 3 * step];
+        dst[i] = a;
+        dst[i + step] = b;
+        dst[i + 2 * step] = c;
+        dst[i + 3 * step] = d;
+    }
+    for (; i < n; i += step) dst[i] = src[i];
 }
 
 inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -339,7 +379,7 @@ inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / k
 
 int plaq_blocks(const Geom &g)
 {
-    const long long need = (2LL * g.Vh + kBlock - 1) / kBlock;
+    const long long need = ((long long)g.Vh + kBlock - 1) / kBlock;
     return (int)(need < kPlaqBlocksMax ? need : kPlaqBlocksMax);
 }
 
@@ -353,16 +393,31 @@ hipError_t launch_start(int precision, void *links, const Geom &g, int hot, uint
     return hipGetLastError();
 }
 
+template <int MU, typename R>
+static void update_launch(store_t<R> *links, const Geom &g, int par, double beta, uint64_t sweep, uint64_t seed,
+                          int nhit, unsigned long long *counters, hipStream_t s)
+{
+    const dim3 grid(blocks_for((long long)g.nlat * g.Vh));
+    const bool dlt = g.nlat == 2;
+    if (nhit == 1 && !dlt)
+        k_update<MU, R, true, false><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters);
+    else if (nhit == 1)
+        k_update<MU, R, true, true><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters);
+    else if (!dlt)
+        k_update<MU, R, false, false><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters);
+    else
+        k_update<MU, R, false, true><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters);
+}
+
 template <typename R>
 static void update_dispatch(store_t<R> *links, const Geom &g, int mu, int par, double beta, uint64_t sweep,
                             uint64_t seed, int nhit, unsigned long long *counters, hipStream_t s)
 {
-    const dim3 grid(blocks_for((long long)g.nlat * g.Vh));
     switch (mu) {
-    case 0: k_update<0, R><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters); break;
-    case 1: k_update<1, R><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters); break;
-    case 2: k_update<2, R><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters); break;
-    default: k_update<3, R><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters); break;
+    case 0: update_launch<0, R>(links, g, par, beta, sweep, seed, nhit, counters, s); break;
+    case 1: update_launch<1, R>(links, g, par, beta, sweep, seed, nhit, counters, s); break;
+    case 2: update_launch<2, R>(links, g, par, beta, sweep, seed, nhit, counters, s); break;
+    default: update_launch<3, R>(links, g, par, beta, sweep, seed, nhit, counters, s); break;
     }
 }
 
@@ -411,7 +466,7 @@ hipError_t launch_gauge(int precision, void *links, const Geom &g, uint64_t gsee
 
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s)
 {
-    k_zero_u64<<<1, 64, 0, s>>>(p, n);
+    k_zero_u64<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(p, n);
     return hipGetLastError();
 }
 
@@ -419,7 +474,7 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s)
 {
     const size_t n = bytes / 16;
     long long want = (long long)((n + kBlock - 1) / kBlock);
-    const unsigned grid = (unsigned)(want < 8192 ? (want > 0 ? want : 1) : 8192);
+    const unsigned grid = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
     k_copy<<<grid, kBlock, 0, s>>>((const uint4 *)src, (uint4 *)dst, n);
     return hipGetLastError();
 }

@@ -9,7 +9,8 @@
 namespace su3hb {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 waves of 64)
-constexpr int kPlaqBlocksMax = 2048; // workgroups per layer of the plaquette reduction
+constexpr int kPlaqBlocksMax = 4096; // workgroups per layer of the plaquette reduction
+constexpr int kCounterSlots = 4096;  // heat-bath counter slots (pairs of u64: attempts, accepts)
 
 int plaq_blocks(const Geom &g);
 

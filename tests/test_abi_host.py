@@ -41,10 +41,10 @@ def test_footprint(hb, L, nlat, prec):
     links, scratch = hb.su3_footprint(p)
     Ls = (L,) * 4 if isinstance(L, int) else L
     V = Ls[0] * Ls[1] * Ls[2] * Ls[3]
-    stride = -(-nlat * V // 2 // 64) * 64
+    stride = -(-nlat * V // 2 // 64) * 64 + 64
     assert links == 72 * stride * (16 if prec == 64 else 8)
     assert links >= 9 * 4 * V * nlat * (16 if prec == 64 else 8)
-    assert 512 < scratch < (1 << 20) and scratch % 256 == 0
+    assert 65536 < scratch < (1 << 20) and scratch % 256 == 0
 
 
 BAD = [dict(L=(3, 4, 4, 4)), dict(L=(0, 4, 4, 4)), dict(L=(2048, 2, 2, 2)), dict(L=4, nlat=3),
