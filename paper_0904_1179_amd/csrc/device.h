@@ -264,6 +264,23 @@ template <typename R> __device__ __forceinline__ M3<R> load_link(const store_t<R
     return m;
 }
 
+// Two links loaded plane by plane in alternation.  Used for pairs of staple
+// links that are the same link for two neighbouring threads (x and x + 2 nu,
+// say): their loads then reach L2 within a few instructions of each other,
+// so the second is an L2 hit instead of a second fetch.
+template <typename R>
+__device__ __forceinline__ void load_link_pair(M3<R> &p, const store_t<R> *bp, int np, M3<R> &q, const store_t<R> *bq,
+                                               int nq, long long stride)
+{
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        const store_t<R> vp = bp[(size_t)e * (size_t)stride + np];
+        const store_t<R> vq = bq[(size_t)e * (size_t)stride + nq];
+        p.e[e / 3][e % 3] = Cx<R>{vp.x, vp.y};
+        q.e[e / 3][e % 3] = Cx<R>{vq.x, vq.y};
+    }
+}
+
 template <typename R> __device__ __forceinline__ void store_link(store_t<R> *base, long long stride, int n, const M3<R> &m)
 {
 #pragma unroll

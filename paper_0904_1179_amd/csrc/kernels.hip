@@ -26,6 +26,9 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 // staple: A += U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+ + U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)
 // written as a (c b)^+ + (e d)^+ f with
 //   a = U_nu(x+mu), b = U_mu(x+nu), c = U_nu(x), d = U_nu(x+mu-nu), e = U_mu(x-nu), f = U_nu(x-nu)
+// Pairs loaded together: (b, e) -- b of thread x is e of thread x + 2 nu;
+// (c, d) -- c of thread x is d of thread x + nu - mu; (a, f) -- a of thread x
+// is f of thread x + mu + nu.
 // ---------------------------------------------------------------------------
 template <int MU, int NU, typename R, bool DLT>
 __device__ __forceinline__ void add_staple(M3<R> &A, const store_t<R> *__restrict__ links, const Geom &g,
@@ -33,25 +36,17 @@ __device__ __forceinline__ void add_staple(M3<R> &A, const store_t<R> *__restric
 {
     if constexpr (NU != MU) {
         const int opp = par ^ 1;
-        {
-            const M3<R> b =
-                load_link<R>(planes<R>(links, g, MU, opp), g.stride, nbr_elem<NU, +1, MU, 0, DLT>(g, x, layer));
-            const M3<R> c = load_link<R>(planes<R>(links, g, NU, par), g.stride, n);
-            const M3<R> cb = mul_nn(c, b);
-            const M3<R> a =
-                load_link<R>(planes<R>(links, g, NU, opp), g.stride, nbr_elem<MU, +1, NU, 0, DLT>(g, x, layer));
-            acc_nd(A, a, cb);
-        }
-        {
-            const M3<R> e =
-                load_link<R>(planes<R>(links, g, MU, opp), g.stride, nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer));
-            const M3<R> d =
-                load_link<R>(planes<R>(links, g, NU, par), g.stride, nbr_elem<MU, +1, NU, -1, DLT>(g, x, layer));
-            const M3<R> ed = mul_nn(e, d);
-            const M3<R> f =
-                load_link<R>(planes<R>(links, g, NU, opp), g.stride, nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer));
-            acc_dn(A, ed, f);
-        }
+        M3<R> b, e, c, d, a, f;
+        load_link_pair<R>(b, planes<R>(links, g, MU, opp), nbr_elem<NU, +1, MU, 0, DLT>(g, x, layer), e,
+                          planes<R>(links, g, MU, opp), nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer), g.stride);
+        load_link_pair<R>(c, planes<R>(links, g, NU, par), n, d, planes<R>(links, g, NU, par),
+                          nbr_elem<MU, +1, NU, -1, DLT>(g, x, layer), g.stride);
+        const M3<R> cb = mul_nn(c, b);
+        const M3<R> ed = mul_nn(e, d);
+        load_link_pair<R>(a, planes<R>(links, g, NU, opp), nbr_elem<MU, +1, NU, 0, DLT>(g, x, layer), f,
+                          planes<R>(links, g, NU, opp), nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer), g.stride);
+        acc_nd(A, a, cb);
+        acc_dn(A, ed, f);
     }
 }
 
@@ -266,17 +261,17 @@ __global__ __launch_bounds__(kBlock) void k_gauge(store_t<R> *__restrict__ links
 // Grid (nblk, nlat); fixed per-thread order, wave shuffles and a fixed
 // per-block order, so the sum is bitwise reproducible.
 // ---------------------------------------------------------------------------
-template <int MU, int NU, typename R>
+template <int MU, int NU, typename R, bool DLT>
 __device__ __forceinline__ double plaq_plane(const store_t<R> *__restrict__ links, const Geom &g, const int x[4],
                                              int layer, int par, int n)
 {
     const int opp = par ^ 1;
     const M3<double> umu = convert<double>(load_link<R>(planes<R>(links, g, MU, par), g.stride, n));
-    const M3<double> unu_xmu =
-        convert<double>(load_link<R>(planes<R>(links, g, NU, opp), g.stride, nbr_elem<MU, +1, NU, 0>(g, x, layer)));
+    const M3<double> unu_xmu = convert<double>(
+        load_link<R>(planes<R>(links, g, NU, opp), g.stride, nbr_elem<MU, +1, NU, 0, DLT>(g, x, layer)));
     const M3<double> unu = convert<double>(load_link<R>(planes<R>(links, g, NU, par), g.stride, n));
-    const M3<double> umu_xnu =
-        convert<double>(load_link<R>(planes<R>(links, g, MU, opp), g.stride, nbr_elem<NU, +1, MU, 0>(g, x, layer)));
+    const M3<double> umu_xnu = convert<double>(
+        load_link<R>(planes<R>(links, g, MU, opp), g.stride, nbr_elem<NU, +1, MU, 0, DLT>(g, x, layer)));
     const M3<double> P = mul_nn(umu, unu_xmu);
     const M3<double> Q = mul_nn(unu, umu_xnu);
     double s = 0.0;
@@ -300,38 +295,45 @@ __device__ __forceinline__ double block_sum(double v)
     return s;
 }
 
-template <typename R>
+template <typename R, bool DLT>
 __device__ __forceinline__ double plaq_site(const store_t<R> *__restrict__ links, const Geom &g, int layer, int par,
                                            int i)
 {
     int x[4];
     site_coords(g, par, i, x);
     const int n = layer * g.Vh + i;
-    double s = plaq_plane<0, 1, R>(links, g, x, layer, par, n);
-    s += plaq_plane<0, 2, R>(links, g, x, layer, par, n);
-    s += plaq_plane<0, 3, R>(links, g, x, layer, par, n);
-    s += plaq_plane<1, 2, R>(links, g, x, layer, par, n);
-    s += plaq_plane<1, 3, R>(links, g, x, layer, par, n);
-    s += plaq_plane<2, 3, R>(links, g, x, layer, par, n);
+    double s = plaq_plane<0, 1, R, DLT>(links, g, x, layer, par, n);
+    s += plaq_plane<0, 2, R, DLT>(links, g, x, layer, par, n);
+    s += plaq_plane<0, 3, R, DLT>(links, g, x, layer, par, n);
+    s += plaq_plane<1, 2, R, DLT>(links, g, x, layer, par, n);
+    s += plaq_plane<1, 3, R, DLT>(links, g, x, layer, par, n);
+    s += plaq_plane<2, 3, R, DLT>(links, g, x, layer, par, n);
     return s;
 }
 
-// Grid (nblk, nlat): thread i of a layer sums the plaquettes of both sites
-// with half-index i (x0 = 2*(i mod L0/2) and its x0 neighbour), so the links
-// of both parities around a tile are read while they are in L2.
-template <typename R>
+// Grid (nblk, nlat).  Workgroup b (XCD-remapped) sums the contiguous run of
+// tiles [b T, (b+1) T) of its layer in the pass order; thread v of a tile
+// takes both sites with half-index i(v) (x0 neighbours), so the links of both
+// parities around a chunk are read while they are in that XCD's L2.  Fixed
+// per-thread order, wave shuffles and a fixed per-block order: the sum is
+// bitwise reproducible.
+template <typename R, bool DLT>
 __global__ __launch_bounds__(kBlock) void k_plaq_partial(const store_t<R> *__restrict__ links, const Geom g,
-                                                         double *__restrict__ partials)
+                                                         const int tiles_per_block, double *__restrict__ partials)
 {
-    const int layer = blockIdx.y;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int layer = DLT ? (int)blockIdx.y : 0;
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
     double s = 0.0;
-    for (int i = tile * kBlock + threadIdx.x; i < g.Vh; i += gridDim.x * kBlock) {
-        s += plaq_site<R>(links, g, layer, 0, i);
-        s += plaq_site<R>(links, g, layer, 1, i);
+    for (int t = 0; t < tiles_per_block; ++t) {
+        const int v = (b * tiles_per_block + t) * kBlock + threadIdx.x;
+        if (v < g.Vh) {
+            const int i = chunk_order(g, v, g.w2);
+            s += plaq_site<R, DLT>(links, g, layer, 0, i);
+            s += plaq_site<R, DLT>(links, g, layer, 1, i);
+        }
     }
-    const double b = block_sum(s);
-    if (threadIdx.x == 0) partials[layer * gridDim.x + blockIdx.x] = b;
+    const double bs = block_sum(s);
+    if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = bs;
 }
 
 // sums[1 + l] = sum over the partials of layer l; sums[0] = sum over layers
@@ -435,11 +437,21 @@ hipError_t launch_plaquette(int precision, const void *links, const Geom &g, dou
                             hipStream_t s)
 {
     const int nblk = plaq_blocks(g);
+    const long long tiles = ((long long)g.Vh + kBlock - 1) / kBlock;
+    const int tpb = (int)((tiles + nblk - 1) / nblk);
     const dim3 grid(nblk, g.nlat);
-    if (precision == 64)
-        k_plaq_partial<double><<<grid, kBlock, 0, s>>>((const double2 *)links, g, partials);
-    else
-        k_plaq_partial<float><<<grid, kBlock, 0, s>>>((const float2 *)links, g, partials);
+    const bool dlt = g.nlat == 2;
+    if (precision == 64) {
+        if (dlt)
+            k_plaq_partial<double, true><<<grid, kBlock, 0, s>>>((const double2 *)links, g, tpb, partials);
+        else
+            k_plaq_partial<double, false><<<grid, kBlock, 0, s>>>((const double2 *)links, g, tpb, partials);
+    } else {
+        if (dlt)
+            k_plaq_partial<float, true><<<grid, kBlock, 0, s>>>((const float2 *)links, g, tpb, partials);
+        else
+            k_plaq_partial<float, false><<<grid, kBlock, 0, s>>>((const float2 *)links, g, tpb, partials);
+    }
     k_plaq_final<<<1, kBlock, 0, s>>>(partials, nblk, g.nlat, sums);
     return hipGetLastError();
 }
