@@ -88,9 +88,9 @@ Geom make_geom(const su3_params *p)
     g.Vh = (int)(V / 2);
     g.nlat = p->nlat;
     g.flip = p->nlat == 2 ? p->flip_mask : 0u;
-    // +64: consecutive planes are offset by 64 elements (1 KiB in FP64) from a
-    // large power-of-two stride, so the 9 entries of a link do not all fall in
-    // the same L2 channel and set
+    // +64: the (direction, parity) blocks are offset by 64 links from a large
+    // power-of-two spacing, so equal positions in different blocks do not all
+    // fall in the same L2 channel and set
     g.stride = round_up((long long)p->nlat * (V / 2), 64) + 64;
     // pass order: x2 cut into chunks of w2 planes, the largest divisor of L2
     // not above L2/8 (one chunk per XCD when L2 is a multiple of 8)
@@ -123,6 +123,12 @@ su3_status check_started(su3_ctx *c)
 }
 
 unsigned long long *counters_of(su3_ctx *c) { return (unsigned long long *)(c->scratch + kOffCounters); }
+
+// device element index of entry e of link n of block (dir, par), in complex numbers
+size_t dev_index(const Geom &g, int dir, int par, int e, long long n)
+{
+    return (size_t)(dir * 2 + par) * (size_t)g.stride * 9 + (size_t)(n >> 4) * 144 + (size_t)e * 16 + (size_t)(n & 15);
+}
 
 // canonical host index of the plane element (dir, par, e, n): maps (layer, parity, i) to site
 void site_of_elem(const Geom &g, int par, long long n, long long *site)
@@ -337,7 +343,7 @@ su3_status su3_get_links(su3_ctx *c, double *host, size_t n_doubles)
             for (int dir = 0; dir < 4; ++dir) {
                 double *dst = host + (size_t)(4 * site + dir) * 18;
                 for (int el = 0; el < 9; ++el) {
-                    const size_t idx = (size_t)((dir * 2 + par) * 9 + el) * (size_t)g.stride + (size_t)n;
+                    const size_t idx = dev_index(g, dir, par, el, n);
                     if (c->p.precision == 64) {
                         const double *v = (const double *)buf.data() + 2 * idx;
                         dst[2 * el] = v[0];
@@ -376,7 +382,7 @@ su3_status su3_set_links(su3_ctx *c, const double *host, size_t n_doubles)
             for (int dir = 0; dir < 4; ++dir) {
                 const double *src = host + (size_t)(4 * site + dir) * 18;
                 for (int el = 0; el < 9; ++el) {
-                    const size_t idx = (size_t)((dir * 2 + par) * 9 + el) * (size_t)g.stride + (size_t)n;
+                    const size_t idx = dev_index(g, dir, par, el, n);
                     if (c->p.precision == 64) {
                         double *v = (double *)buf.data() + 2 * idx;
                         v[0] = src[2 * el];
@@ -432,7 +438,7 @@ su3_status su3_get_link_sample(su3_ctx *c, const uint64_t *lids, size_t n, doubl
         const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
         const size_t elem = (size_t)layer * (size_t)g.Vh + (size_t)((site % c->V) >> 1);
         for (int el = 0; el < 9; ++el) {
-            const size_t idx = (size_t)((dir * 2 + par) * 9 + el) * (size_t)g.stride + elem;
+            const size_t idx = dev_index(g, dir, par, el, (long long)elem);
             hipError_t e = hipMemcpyAsync(buf.data() + (k * 9 + el) * esz, (const unsigned char *)c->links + idx * esz,
                                           esz, hipMemcpyDeviceToHost, c->stream);
             if (e != hipSuccess) return hip_fail(e, "sample copy");

@@ -160,7 +160,7 @@ struct Geom {
     int Vh;             // V / 2
     int nlat;
     unsigned flip;      // layer-switch mask, 0 on a single torus
-    long long stride;   // elements per component plane (>= nlat * Vh, multiple of 64)
+    long long stride;   // links per (direction, parity) block (>= nlat * Vh, multiple of 64)
     int w2;             // chunk width of the pass order (divides L2)
 };
 
@@ -242,53 +242,75 @@ __device__ __forceinline__ int chunk_order(const Geom &g, int v, int w2)
     return x0h + l0h * (x1 + g.L[1] * (x2 + g.L[2] * x3));
 }
 
-// Base of the 9 planes of (direction, parity).
+// Link storage.  The links of one (direction, parity) form a block of
+// `stride` links in tiles of kTile = 16 consecutive links; a tile holds the 9
+// complex entries as 9 rows of 16 (entry-major inside the tile):
+//   element (dir, par, n, e) at block(dir, par) + (n / 16) * 144 + e * 16 + n % 16.
+// A wave of 64 consecutive links reads 4 tiles, 256 contiguous bytes (FP64)
+// per tile and entry: whole cache lines.  The 9 loads of one link share a
+// single per-lane address and differ by the compile-time offset e * 16
+// elements, which the load instruction encodes as an immediate.
+constexpr int kTile = 16;
+
 template <typename R>
 __device__ __forceinline__ const store_t<R> *planes(const store_t<R> *links, const Geom &g, int dir, int par)
 {
-    return links + (size_t)((dir * 2 + par) * 9) * (size_t)g.stride;
+    return links + (size_t)(dir * 2 + par) * (size_t)g.stride * 9;
 }
 template <typename R> __device__ __forceinline__ store_t<R> *planes(store_t<R> *links, const Geom &g, int dir, int par)
 {
-    return links + (size_t)((dir * 2 + par) * 9) * (size_t)g.stride;
+    return links + (size_t)(dir * 2 + par) * (size_t)g.stride * 9;
 }
 
-template <typename R> __device__ __forceinline__ M3<R> load_link(const store_t<R> *base, long long stride, int n)
+// entry 0 of link n in its block; entry e is at + e * kTile
+template <typename R> __device__ __forceinline__ const store_t<R> *link_at(const store_t<R> *block, int n)
+{
+    return block + (size_t)(n >> 4) * (9 * kTile) + (n & (kTile - 1));
+}
+template <typename R> __device__ __forceinline__ store_t<R> *link_at(store_t<R> *block, int n)
+{
+    return block + (size_t)(n >> 4) * (9 * kTile) + (n & (kTile - 1));
+}
+
+template <typename R> __device__ __forceinline__ M3<R> load_link(const store_t<R> *block, long long, int n)
 {
     M3<R> m;
+    const store_t<R> *p = link_at<R>(block, n);
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
-        const store_t<R> v = base[(size_t)e * (size_t)stride + n];
+        const store_t<R> v = p[e * kTile];
         m.e[e / 3][e % 3] = Cx<R>{v.x, v.y};
     }
     return m;
 }
 
-// Two links loaded plane by plane in alternation.  Used for pairs of staple
+// Two links loaded entry by entry in alternation.  Used for pairs of staple
 // links that are the same link for two neighbouring threads (x and x + 2 nu,
 // say): their loads then reach L2 within a few instructions of each other,
 // so the second is an L2 hit instead of a second fetch.
 template <typename R>
 __device__ __forceinline__ void load_link_pair(M3<R> &p, const store_t<R> *bp, int np, M3<R> &q, const store_t<R> *bq,
-                                               int nq, long long stride)
+                                               int nq, long long)
 {
+    const store_t<R> *pp = link_at<R>(bp, np), *pq = link_at<R>(bq, nq);
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
-        const store_t<R> vp = bp[(size_t)e * (size_t)stride + np];
-        const store_t<R> vq = bq[(size_t)e * (size_t)stride + nq];
+        const store_t<R> vp = pp[e * kTile];
+        const store_t<R> vq = pq[e * kTile];
         p.e[e / 3][e % 3] = Cx<R>{vp.x, vp.y};
         q.e[e / 3][e % 3] = Cx<R>{vq.x, vq.y};
     }
 }
 
-template <typename R> __device__ __forceinline__ void store_link(store_t<R> *base, long long stride, int n, const M3<R> &m)
+template <typename R> __device__ __forceinline__ void store_link(store_t<R> *block, long long, int n, const M3<R> &m)
 {
+    store_t<R> *p = link_at<R>(block, n);
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
         store_t<R> v;
         v.x = m.e[e / 3][e % 3].re;
         v.y = m.e[e / 3][e % 3].im;
-        base[(size_t)e * (size_t)stride + n] = v;
+        p[e * kTile] = v;
     }
 }
 

@@ -261,6 +261,8 @@ __global__ __launch_bounds__(kBlock) void k_gauge(store_t<R> *__restrict__ links
 // Grid (nblk, nlat); fixed per-thread order, wave shuffles and a fixed
 // per-block order, so the sum is bitwise reproducible.
 // ---------------------------------------------------------------------------
+// Re Tr U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+ = Re Tr P Q^+ with
+// P = U_mu(x) U_nu(x+mu), Q = U_nu(x) U_mu(x+nu), in FP64.
 template <int MU, int NU, typename R, bool DLT>
 __device__ __forceinline__ double plaq_plane(const store_t<R> *__restrict__ links, const Geom &g, const int x[4],
                                              int layer, int par, int n)
