@@ -1,0 +1,141 @@
+"""GPU tests of the workload configurations and of the FP32 tier against the
+FP64 oracle.
+
+FP32 tier: links stored and multiplied in FP32; heat-bath scalars,
+reunitarisation, plaquette products and sums in FP64.  Its error against the
+FP64 oracle is stated per result: plaquette relative error <= 1e-5 over the
+first sweeps from the same start (FP32 rounding of the links is ~6e-8 and
+grows slowly along the chain), and agreement of long-run averages within the
+statistical error once the two chains have decorrelated.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def hb():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0904_1179_amd as hb_
+
+    return hb_
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _binned(x, nbins=20):
+    x = np.asarray(x)
+    m = len(x) // nbins
+    b = x[: m * nbins].reshape(nbins, m).mean(axis=1)
+    return x.mean(), b.std(ddof=1) / np.sqrt(nbins)
+
+
+@pytest.mark.parametrize("L,nlat", [(16, 1), ((8, 8, 8, 16), 2)])
+def test_fp32_first_sweeps_against_fp64_oracle(hb, L, nlat):
+    from oracle import su3ref
+
+    _say(f"fp32 first sweeps L={L} nlat={nlat}")
+    lat = hb.Lattice(L, nlat=nlat, precision=32, seed=5)
+    ref = su3ref.Oracle(L, nlat=nlat, seed=5)
+    lat.start(True)
+    ref.start(True)
+    for s in range(4):
+        lat.sweep(1, 5.7)
+        ref.sweep(1, 5.7)
+        p32, p64 = lat.plaquette(), ref.plaquette()
+        rel = np.abs(p32 - p64) / np.abs(p64)
+        dev = np.abs(lat.get_links() - ref.links()).max(axis=1)
+        _say(f"  sweep {s + 1}: plaquette rel err {rel.max():.2e}, median link dev {np.median(dev):.1e}, "
+             f"links dev > 1e-3: {(dev > 1e-3).sum()} of {len(dev)}")
+        assert rel.max() <= 1e-5
+        assert np.median(dev) < 1e-5
+    U = su3ref.to_complex(lat.get_links())
+    # FP32 storage: unitarity at FP32 rounding, reunitarised in FP64 before every store
+    assert np.abs(U @ U.conj().transpose(0, 2, 1) - np.eye(3)).max() < 1e-6
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_long_run_average_matches_oracle(hb, precision):
+    """8^4, beta 5.7, cold start, 50 thermalisation + 400 measured sweeps:
+    GPU and oracle mean plaquettes agree within 4 combined standard errors."""
+    from oracle import su3ref
+
+    _say(f"long run precision={precision}")
+    lat = hb.Lattice(8, precision=precision, seed=21)
+    lat.start(False)
+    lat.sweep(50, 5.7)
+    g = []
+    for _ in range(400):
+        lat.sweep(1, 5.7)
+        g.append(lat.plaquette()[0])
+    ref = su3ref.Oracle(8, seed=77)  # an independent chain
+    ref.start(False)
+    ref.sweep(50, 5.7)
+    o = []
+    for _ in range(400):
+        ref.sweep(1, 5.7)
+        o.append(ref.plaquette()[0])
+    mg, eg = _binned(g)
+    mo, eo = _binned(o)
+    _say(f"  GPU {mg:.6f} +- {eg:.6f}, oracle {mo:.6f} +- {eo:.6f}")
+    assert abs(mg - mo) < 4 * np.hypot(eg, eo)
+    _, att, acc = lat.counters()
+    assert 0.96 < acc / att < 0.98  # the paper's 97.2 % 1-hit acceptance at beta = 5.7
+
+
+def test_dlt_config_per_layer_plaquette_table(hb):
+    """2 x 16^4 DLT (flip 0x7), beta 5.7, FP64, hot start, 32 sweeps: per-layer
+    plaquette after every sweep against the oracle, counters exact."""
+    from oracle import su3ref
+
+    _say("DLT 2x16^4 32 sweeps")
+    lat = hb.Lattice(16, nlat=2, flip_mask=0x7, seed=1)
+    ref = su3ref.Oracle(16, nlat=2, flip_mask=0x7, seed=1)
+    lat.start(True)
+    ref.start(True)
+    worst = 0.0
+    for s in range(32):
+        lat.sweep(1, 5.7)
+        ref.sweep(1, 5.7)
+        d = np.abs(lat.plaquette() - ref.plaquette()).max()
+        worst = max(worst, d)
+        assert d < 1e-10, f"sweep {s + 1}: {d:.2e}"
+        assert lat.counters()[1:] == ref.counters()
+    p = lat.plaquette()
+    _say(f"  per-layer plaquette after 32 sweeps {p[1]:.6f} {p[2]:.6f}, worst |dP| {worst:.1e}")
+    assert abs(p[1] - p[2]) < 0.01  # the two layers are equivalent under the gluing
+
+
+def test_64_config_beta6_sampled(hb):
+    """64^4, beta 6.0, FP64 and FP32, hot start: sampled links after the first
+    sweep against the oracle computed link by link."""
+    from cone import FirstSweepCone, sample_lids
+    from oracle import su3ref
+
+    _say("64^4 beta 6.0 sampled")
+    lids = sample_lids(4 * 64 ** 4, 24, seed=6)
+    cone = FirstSweepCone(64, seed=1, beta=6.0)
+    ref = np.array([cone.value(l) for l in lids])
+    for precision, tol in ((64, 1e-12), (32, 1e-4)):
+        lat = hb.Lattice(64, precision=precision, seed=1)
+        lat.start(True)
+        lat.sweep(1, 6.0)
+        got = su3ref.to_complex(lat.link_sample(lids))
+        dev = np.abs(got - ref).max(axis=(1, 2))
+        _say(f"  precision {precision}: max link dev {dev.max():.2e}")
+        assert np.median(dev) < tol
+        if precision == 64:
+            assert dev.max() < tol
+        del lat
