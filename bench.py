@@ -14,7 +14,8 @@ Also reported on the same JSON line:
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
   fp32          the FP32-link tier on the same workload and its plaquette
                 deviation from the FP64 chain
-  serving       the mixed job stream (p50/p99 latency), when --serving is given
+  serving       the mixed job stream through the job server: p50/p99 latency
+                (arrival to completion) and throughput
 """
 import argparse
 import hashlib
@@ -163,7 +164,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
-    ap.add_argument("--serving", action="store_true", help="also run the mixed job stream")
+    ap.add_argument("--no-serving", action="store_true", help="skip the mixed job stream")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -215,7 +216,7 @@ def main():
                        "plaquette_rel_err_vs_fp64_per_sweep": fp32_deviation(L, beta),
                        "note": "FP32 links and products; FP64 heat-bath scalars, reunitarisation and sums"}
 
-    if args.serving:
+    if not args.no_serving:
         from paper_0904_1179_amd.serve import run_stream_benchmark
 
         out["serving"] = run_stream_benchmark()

@@ -142,6 +142,55 @@ su3_status su3_destroy(su3_ctx *c);
  * stream with 16-byte vector loads and stores.  Asynchronous. */
 su3_status su3_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Job server: continuous batching of many independent lattices on one GPU.
+ *
+ * The caller gives the server one device buffer, its HBM budget.  Submitted
+ * jobs wait in submission order and are admitted when fewer than max_active
+ * jobs run and a first-fit allocation of the job's footprint (su3_footprint:
+ * links + scratch) succeeds inside the buffer.  Each su3_server_step admits
+ * what fits, runs one sweep of every admitted job -- 8 batched launches, one
+ * per checkerboard pass, each covering all jobs of a precision -- and retires
+ * the jobs that reached their sweep count (final plaquette and heat-bath
+ * counters kept, memory freed).  A job's links get the same per-link
+ * arithmetic and the same keyed random numbers as a single lattice run with
+ * su3_start/su3_sweep, so its result is the same alone and in the mix.
+ * su3_server_step synchronises the server's stream.
+ * ------------------------------------------------------------------------ */
+typedef struct su3_server su3_server;
+
+typedef struct {
+    su3_params params; /* lattice, precision, nhit and Philox key of the job */
+    double beta;       /* coupling, finite and > 0 */
+    int32_t nsweeps;   /* sweeps to run, >= 1 */
+    int32_t hot;       /* start: 0 cold, 1 Haar hot */
+} su3_job;
+
+typedef enum { SU3_JOB_QUEUED = 0, SU3_JOB_ACTIVE = 1, SU3_JOB_DONE = 2 } su3_job_state;
+
+typedef struct {
+    int32_t state;        /* su3_job_state */
+    int32_t sweeps_done;
+    double plaquette[3];  /* once done: total, then per layer (as su3_plaquette) */
+    uint64_t kp_attempts; /* once done */
+    uint64_t kp_accepts;
+} su3_job_result;
+
+/* d_arena: device buffer of arena_bytes, 256-byte aligned; the server keeps
+ * its job tables at the start and allocates job footprints from the rest.
+ * max_active in [1, 4096].  SU3_ENOSPC if the arena cannot hold the tables. */
+su3_status su3_server_create(void *d_arena, size_t arena_bytes, int32_t max_active, void *hip_stream,
+                             su3_server **out);
+/* Queue a job; SU3_EINVAL for invalid parameters, SU3_ENOSPC if its footprint
+ * exceeds the whole arena (it could never be admitted). */
+su3_status su3_server_submit(su3_server *s, const su3_job *job, int64_t *job_id);
+/* Admit, run one batched sweep, retire; counts after the step (any pointer may be NULL). */
+su3_status su3_server_step(su3_server *s, int32_t *n_active, int32_t *n_queued, int32_t *n_finished);
+su3_status su3_server_poll(su3_server *s, int64_t job_id, su3_job_result *out);
+su3_status su3_server_stats(su3_server *s, size_t *arena_used, size_t *arena_peak, uint64_t *steps);
+/* Waits for the stream, frees host resources; never frees the arena. */
+su3_status su3_server_destroy(su3_server *s);
+
 const char *su3_strerror(su3_status s);
 const char *su3_last_error(void);
 

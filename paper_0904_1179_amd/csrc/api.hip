@@ -14,13 +14,11 @@
 #include <vector>
 
 #include "../../include/su3hb.h"
-#include "launch.h"
-
-using su3hb::Geom;
+#include "runtime.h"
 
 struct su3_ctx {
     su3_params p;
-    Geom g;
+    su3hb::Geom g;
     size_t V;
     void *links;
     size_t link_bytes;
@@ -36,9 +34,12 @@ struct su3_ctx {
     size_t ev_used;
 };
 
-namespace {
+namespace su3hb {
 
+namespace {
 thread_local std::string g_last_error;
+long long round_up(long long a, long long m) { return (a + m - 1) / m * m; }
+}  // namespace
 
 su3_status fail(su3_status s, const std::string &msg)
 {
@@ -51,14 +52,7 @@ su3_status hip_fail(hipError_t e, const char *where)
     return fail(SU3_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-// scratch layout (bytes): [0, 16*kCounterSlots) heat-bath counter slots (pairs
-// of u64 attempts, accepts); then 256 bytes of plaquette sums; then the
-// plaquette partials
-constexpr size_t kOffCounters = 0;
-constexpr size_t kOffSums = 16 * (size_t)su3hb::kCounterSlots;
-constexpr size_t kOffPartials = kOffSums + 256;
-
-long long round_up(long long a, long long m) { return (a + m - 1) / m * m; }
+const char *last_error() { return g_last_error.c_str(); }
 
 su3_status check_params(const su3_params *p)
 {
@@ -82,7 +76,7 @@ su3_status check_params(const su3_params *p)
 
 Geom make_geom(const su3_params *p)
 {
-    Geom g;
+    su3hb::Geom g;
     for (int mu = 0; mu < 4; ++mu) g.L[mu] = p->L[mu];
     const long long V = (long long)p->L[0] * p->L[1] * p->L[2] * p->L[3];
     g.Vh = (int)(V / 2);
@@ -107,8 +101,14 @@ size_t link_bytes_of(const su3_params *p, const Geom &g)
 
 size_t scratch_bytes_of(const Geom &g)
 {
-    return (size_t)round_up(kOffPartials + 8LL * g.nlat * su3hb::plaq_blocks(g), 256);
+    return (size_t)round_up(kOffPartials + 8LL * g.nlat * plaq_blocks(g), 256);
 }
+
+}  // namespace su3hb
+
+using namespace su3hb;
+
+namespace {
 
 su3_status check_ctx(su3_ctx *c)
 {
@@ -163,7 +163,7 @@ const char *su3_strerror(su3_status s)
     return "unknown status";
 }
 
-const char *su3_last_error(void) { return g_last_error.c_str(); }
+const char *su3_last_error(void) { return su3hb::last_error(); }
 
 su3_status su3_footprint(const su3_params *p, size_t *link_bytes, size_t *scratch_bytes)
 {

@@ -129,34 +129,36 @@ __device__ __forceinline__ void heatbath(M3<R> &U, const M3<R> &A, double beta, 
     U = convert<R>(Ud);
 }
 
+// One thread of a pass: the link U_MU at pass-order position v of its layer
+// (v < nlat * Vh).  Shared by the single-lattice and the batched kernels, so
+// a lattice gets bit-identical updates from both.
 template <int MU, typename R, bool HIT1, bool DLT>
-__global__ __launch_bounds__(kBlock) void k_update(store_t<R> *__restrict__ links, const Geom g, const int par,
-                                                   const double beta, const uint64_t sweep, const uint64_t seed,
-                                                   const int nhit, unsigned long long *__restrict__ counters)
+__device__ __forceinline__ void update_link(store_t<R> *__restrict__ links, const Geom &g, int par, int v, double beta,
+                                            uint64_t sweep, uint64_t seed, int nhit, int &att, int &acc)
 {
-    const int v = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    int att = 0, acc = 0;
-    if (v < g.nlat * g.Vh) {
-        const int layer = DLT && v >= g.Vh ? 1 : 0;
-        const int i = chunk_order(g, v - layer * g.Vh, g.w2);
-        const int n = layer * g.Vh + i;
-        int x[4];
-        site_coords(g, par, i, x);
-        M3<R> A;
-        set_zero(A);
-        add_staple<MU, 0, R, DLT>(A, links, g, x, layer, par, n);
-        add_staple<MU, 1, R, DLT>(A, links, g, x, layer, par, n);
-        add_staple<MU, 2, R, DLT>(A, links, g, x, layer, par, n);
-        add_staple<MU, 3, R, DLT>(A, links, g, x, layer, par, n);
-        store_t<R> *own = planes<R>(links, g, MU, par);
-        M3<R> U = load_link<R>(own, g.stride, n);
-        const uint64_t site = (uint64_t)layer * (uint64_t)(2 * g.Vh) + (uint64_t)lex_of(g, x);
-        heatbath<R, HIT1>(U, A, beta, seed, 4 * site + MU, sweep, nhit, att, acc);
-        store_link<R>(own, g.stride, n, U);
-    }
-    // exact integer counts: packed (attempts | accepts << 16) summed over the
-    // workgroup, then added to counter slot blockIdx % kCounterSlots, so no two
-    // concurrent workgroups update the same address
+    const int layer = DLT && v >= g.Vh ? 1 : 0;
+    const int i = chunk_order(g, v - layer * g.Vh, g.w2);
+    const int n = layer * g.Vh + i;
+    int x[4];
+    site_coords(g, par, i, x);
+    M3<R> A;
+    set_zero(A);
+    add_staple<MU, 0, R, DLT>(A, links, g, x, layer, par, n);
+    add_staple<MU, 1, R, DLT>(A, links, g, x, layer, par, n);
+    add_staple<MU, 2, R, DLT>(A, links, g, x, layer, par, n);
+    add_staple<MU, 3, R, DLT>(A, links, g, x, layer, par, n);
+    store_t<R> *own = planes<R>(links, g, MU, par);
+    M3<R> U = load_link<R>(own, g.stride, n);
+    const uint64_t site = (uint64_t)layer * (uint64_t)(2 * g.Vh) + (uint64_t)lex_of(g, x);
+    heatbath<R, HIT1>(U, A, beta, seed, 4 * site + MU, sweep, nhit, att, acc);
+    store_link<R>(own, g.stride, n, U);
+}
+
+// Exact integer heat-bath counts: packed (attempts | accepts << 16) summed
+// over the workgroup, then added to counter slot `slot`, so no two
+// concurrent workgroups update the same address.
+__device__ __forceinline__ void count_block(int att, int acc, unsigned long long *__restrict__ counters, int slot)
+{
     unsigned packed = (unsigned)att | ((unsigned)acc << 16);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) packed += __shfl_xor(packed, off);
@@ -171,11 +173,52 @@ __global__ __launch_bounds__(kBlock) void k_update(store_t<R> *__restrict__ link
             b += wsum[w] >> 16;
         }
         if (a != 0) {
-            unsigned long long *slot = counters + 2 * (blockIdx.x % kCounterSlots);
-            atomicAdd(&slot[0], a);
-            atomicAdd(&slot[1], b);
+            unsigned long long *c = counters + 2 * slot;
+            atomicAdd(&c[0], a);
+            atomicAdd(&c[1], b);
         }
     }
+}
+
+template <int MU, typename R, bool HIT1, bool DLT>
+__global__ __launch_bounds__(kBlock) void k_update(store_t<R> *__restrict__ links, const Geom g, const int par,
+                                                   const double beta, const uint64_t sweep, const uint64_t seed,
+                                                   const int nhit, unsigned long long *__restrict__ counters)
+{
+    const int v = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    int att = 0, acc = 0;
+    if (v < g.nlat * g.Vh) update_link<MU, R, HIT1, DLT>(links, g, par, v, beta, sweep, seed, nhit, att, acc);
+    count_block(att, acc, counters, blockIdx.x % kCounterSlots);
+}
+
+// Batched pass: one launch updates the links U_MU of parity `par` of every
+// job in `jobs` (sorted by tile_begin).  Workgroup b belongs to the job whose
+// tile range holds b; job j is at sweep index sweep0 + (step - admit_step).
+template <int MU, typename R, bool HIT1>
+__global__ __launch_bounds__(kBlock) void k_update_batch(const BatchJob *__restrict__ jobs, const int njobs,
+                                                         const long long step, const int par)
+{
+    __shared__ int sj;
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].tile_begin <= (int)blockIdx.x)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        sj = lo;
+    }
+    __syncthreads();
+    const BatchJob &J = jobs[sj];
+    const int local = (int)blockIdx.x - J.tile_begin;
+    const int v = local * kBlock + threadIdx.x;
+    const uint64_t sweep = J.sweep0 + (uint64_t)(step - J.admit_step);
+    int att = 0, acc = 0;
+    if (v < J.g.nlat * J.g.Vh)
+        update_link<MU, R, HIT1, true>((store_t<R> *)J.links, J.g, par, v, J.beta, sweep, J.seed, J.nhit, att, acc);
+    count_block(att, acc, J.counters, local % kCounterSlots);
 }
 
 // ---------------------------------------------------------------------------
@@ -432,6 +475,35 @@ hipError_t launch_update(int precision, void *links, const Geom &g, int mu, int 
         update_dispatch<double>((double2 *)links, g, mu, par, beta, sweep, seed, nhit, counters, s);
     else
         update_dispatch<float>((float2 *)links, g, mu, par, beta, sweep, seed, nhit, counters, s);
+    return hipGetLastError();
+}
+
+template <typename R, bool HIT1>
+static void batch_dispatch(const BatchJob *jobs, int njobs, int ntiles, long long step, int mu, int par, hipStream_t s)
+{
+    switch (mu) {
+    case 0: k_update_batch<0, R, HIT1><<<ntiles, kBlock, 0, s>>>(jobs, njobs, step, par); break;
+    case 1: k_update_batch<1, R, HIT1><<<ntiles, kBlock, 0, s>>>(jobs, njobs, step, par); break;
+    case 2: k_update_batch<2, R, HIT1><<<ntiles, kBlock, 0, s>>>(jobs, njobs, step, par); break;
+    default: k_update_batch<3, R, HIT1><<<ntiles, kBlock, 0, s>>>(jobs, njobs, step, par); break;
+    }
+}
+
+hipError_t launch_update_batch(int precision, bool hit1, const BatchJob *d_jobs, int njobs, int ntiles, long long step,
+                               int mu, int par, hipStream_t s)
+{
+    if (njobs <= 0 || ntiles <= 0) return hipSuccess;
+    if (precision == 64) {
+        if (hit1)
+            batch_dispatch<double, true>(d_jobs, njobs, ntiles, step, mu, par, s);
+        else
+            batch_dispatch<double, false>(d_jobs, njobs, ntiles, step, mu, par, s);
+    } else {
+        if (hit1)
+            batch_dispatch<float, true>(d_jobs, njobs, ntiles, step, mu, par, s);
+        else
+            batch_dispatch<float, false>(d_jobs, njobs, ntiles, step, mu, par, s);
+    }
     return hipGetLastError();
 }
 

@@ -14,9 +14,26 @@ constexpr int kCounterSlots = 4096;  // heat-bath counter slots (pairs of u64: a
 
 int plaq_blocks(const Geom &g);
 
+// One job of a batched pass (continuous batching of several lattices).
+struct BatchJob {
+    void *links;                   // this job's link buffer (tiled layout, its own precision)
+    unsigned long long *counters;  // this job's heat-bath counter slots
+    Geom g;
+    double beta;
+    uint64_t seed;
+    uint64_t sweep0;               // sweep index at global step admit_step
+    long long admit_step;
+    int nhit;
+    int tile_begin;                // first workgroup of this job in the launch
+};
+
 hipError_t launch_start(int precision, void *links, const Geom &g, int hot, uint64_t seed, hipStream_t s);
 hipError_t launch_update(int precision, void *links, const Geom &g, int mu, int par, double beta, uint64_t sweep,
                          uint64_t seed, int nhit, unsigned long long *counters, hipStream_t s);
+// one pass (mu, par) of every job in d_jobs (device copy, sorted by tile_begin);
+// all jobs share `precision`; hit1: every job has nhit = 1
+hipError_t launch_update_batch(int precision, bool hit1, const BatchJob *d_jobs, int njobs, int ntiles, long long step,
+                               int mu, int par, hipStream_t s);
 hipError_t launch_plaquette(int precision, const void *links, const Geom &g, double *partials, double *sums,
                             hipStream_t s);
 hipError_t launch_reunit(int precision, void *links, const Geom &g, hipStream_t s);
