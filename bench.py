@@ -28,8 +28,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
-LINK_BYTES = {64: 144, 32: 72}  # one SU(3) matrix, 18 reals
-TRANSFERS_PER_UPDATE = 9  # each pass reads all 4*V*nlat links and writes V*nlat/2 of them
+REAL_BYTES = {64: 8, 32: 4}
+# Algorithmic bytes of one link update in a pass: the pass reads every link of
+# the lattice once (8 reads per updated link) and writes the updated link.
+# Reads take rows 0 and 1 (12 reals; row 2 is rebuilt), writes all 18 reals.
+READ_REALS, WRITE_REALS, READS_PER_UPDATE = 12, 18, 8
+
+
+def bytes_per_update(precision):
+    return (READS_PER_UPDATE * READ_REALS + WRITE_REALS) * REAL_BYTES[precision]
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0904_1179_amd", "csrc", f) for f in ("kernels.hip", "device.h")]
 
@@ -181,13 +188,14 @@ def main():
     ups = main_run["updates"] / main_run["seconds"]
     pass_s = main_run["pass_ms"] * 1e-3
     links_per_pass = L ** 4 // 2
-    alg_bytes = TRANSFERS_PER_UPDATE * LINK_BYTES[prec] * links_per_pass
+    alg_bytes = bytes_per_update(prec) * links_per_pass
     achieved = alg_bytes / pass_s / 1e9
     traffic = stored_traffic(f"k_update_{L}x4_fp{prec}_traffic.txt")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": f"k_update<mu, {'double' if prec == 64 else 'float'}>",
-                "algorithmic_bytes_per_launch": alg_bytes, "launch_us": round(main_run["pass_ms"] * 1e3, 2),
+                "algorithmic_bytes_per_launch": alg_bytes, "algorithmic_bytes_per_update": bytes_per_update(prec),
+                "updates_per_s_vs_18_real_roofline": round(links_per_pass / pass_s / (HBM_PEAK_GBS * 1e9 / (9 * 18 * REAL_BYTES[prec])), 4), "launch_us": round(main_run["pass_ms"] * 1e3, 2),
                 "launches_timed": main_run["passes"]}
     if not args.no_copy_probe:
         roofline["copy_probe_gbs"] = round(copy_probe_gbs(), 1)
@@ -209,7 +217,7 @@ def main():
         r32 = run_gpu(L, 32, args.steps, args.warmup, beta)
         del r32["lattice"]
         v32 = r32["updates"] / r32["seconds"]
-        alg32 = TRANSFERS_PER_UPDATE * LINK_BYTES[32] * links_per_pass
+        alg32 = bytes_per_update(32) * links_per_pass
         out["fp32"] = {"value": v32, "unit": "link updates/s", "speedup_vs_fp64": v32 / ups,
                        "launch_us": round(r32["pass_ms"] * 1e3, 2),
                        "achieved_gbs": round(alg32 / (r32["pass_ms"] * 1e-3) / 1e9, 1),

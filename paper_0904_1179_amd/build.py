@@ -1,10 +1,14 @@
-"""Build libsu3hb.so: the gfx950 HIP kernels and the C-ABI host runtime.
+"""Build libsu3hb.so: the gfx950 HIP kernels, the C-ABI host runtime and the
+job server.
 
-hipcc cross-compiles for gfx950 without a GPU.  Packed-FP32 instructions are
-disabled for all device code (-packed-fp32-ops); FP64 code is unaffected.
+hipcc cross-compiles for gfx950 without a GPU; each source is compiled in its
+own process, then linked.  Packed-FP32 instructions are disabled for all
+device code (-packed-fp32-ops); FP64 code is unaffected.
 """
 import os
 import subprocess
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -12,19 +16,27 @@ LIB = os.path.join(HERE, "libsu3hb.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "api.hip", "server.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-I" + os.path.join(ROOT, "include")]
+COMPILE = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-I" + os.path.join(ROOT, "include")]
 
 
-def build() -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + SOURCES
+def _run(cmd):
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in res.stdout.splitlines() if "packed-fp32-ops" not in l)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + out)
-    os.replace(tmp, LIB)
+        raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + out)
+    return out
+
+
+def build() -> str:
+    with tempfile.TemporaryDirectory(prefix="su3hb_build_") as tmp:
+        objs = [os.path.join(tmp, os.path.basename(s) + ".o") for s in SOURCES]
+        with ThreadPoolExecutor(max_workers=len(SOURCES)) as pool:
+            list(pool.map(_run, [[HIPCC] + COMPILE + ["-c", src, "-o", obj] for src, obj in zip(SOURCES, objs)]))
+        out = LIB + ".tmp"
+        _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out] + objs)
+        os.replace(out, LIB)
     return LIB
 
 

@@ -302,6 +302,51 @@ __device__ __forceinline__ void load_link_pair(M3<R> &p, const store_t<R> *bp, i
     }
 }
 
+// row 2 = conj(row 0 x row 1): the third row of an SU(3) matrix, computed
+// exactly as reunit() computes it
+template <typename R> __device__ __forceinline__ void rebuild_row2(M3<R> &u)
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int a = (k + 1) % 3, b = (k + 2) % 3;
+        const Cx<R> p = cmul(u.e[0][a], u.e[1][b]), q = cmul(u.e[0][b], u.e[1][a]);
+        u.e[2][k] = Cx<R>{p.re - q.re, -(p.im - q.im)};
+    }
+}
+
+// Reads of links produced by this library: only rows 0 and 1 (6 of the 9
+// entries, 2/3 of the bytes) are loaded and row 2 is rebuilt.  Every stored
+// link was reunitarised with the same row-2 formula, so the rebuilt row
+// equals the stored one up to the rounding of that formula.
+template <typename R> __device__ __forceinline__ M3<R> load_link12(const store_t<R> *block, int n)
+{
+    M3<R> m;
+    const store_t<R> *p = link_at<R>(block, n);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        const store_t<R> v = p[e * kTile];
+        m.e[e / 3][e % 3] = Cx<R>{v.x, v.y};
+    }
+    rebuild_row2(m);
+    return m;
+}
+
+template <typename R>
+__device__ __forceinline__ void load_link12_pair(M3<R> &p, const store_t<R> *bp, int np, M3<R> &q,
+                                                 const store_t<R> *bq, int nq)
+{
+    const store_t<R> *pp = link_at<R>(bp, np), *pq = link_at<R>(bq, nq);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        const store_t<R> vp = pp[e * kTile];
+        const store_t<R> vq = pq[e * kTile];
+        p.e[e / 3][e % 3] = Cx<R>{vp.x, vp.y};
+        q.e[e / 3][e % 3] = Cx<R>{vq.x, vq.y};
+    }
+    rebuild_row2(p);
+    rebuild_row2(q);
+}
+
 template <typename R> __device__ __forceinline__ void store_link(store_t<R> *block, long long, int n, const M3<R> &m)
 {
     store_t<R> *p = link_at<R>(block, n);
@@ -352,12 +397,8 @@ __device__ __forceinline__ void reunit(M3<double> &u)
         r1[k].im /= n1;
     }
     // r2_k = conj(r0_{k+1} r1_{k+2} - r0_{k+2} r1_{k+1})
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int a = (k + 1) % 3, b = (k + 2) % 3;
-        const Cx<double> p = cmul(r0[a], r1[b]), q = cmul(r0[b], r1[a]);
-        r2[k] = Cx<double>{p.re - q.re, -(p.im - q.im)};
-    }
+    (void)r2;
+    rebuild_row2(u);
 }
 
 // Haar-random SU(3) element keyed by (seed; id, 0, draw, tag): 12 normals by

@@ -37,14 +37,14 @@ __device__ __forceinline__ void add_staple(M3<R> &A, const store_t<R> *__restric
     if constexpr (NU != MU) {
         const int opp = par ^ 1;
         M3<R> b, e, c, d, a, f;
-        load_link_pair<R>(b, planes<R>(links, g, MU, opp), nbr_elem<NU, +1, MU, 0, DLT>(g, x, layer), e,
-                          planes<R>(links, g, MU, opp), nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer), g.stride);
-        load_link_pair<R>(c, planes<R>(links, g, NU, par), n, d, planes<R>(links, g, NU, par),
-                          nbr_elem<MU, +1, NU, -1, DLT>(g, x, layer), g.stride);
+        load_link12_pair<R>(b, planes<R>(links, g, MU, opp), nbr_elem<NU, +1, MU, 0, DLT>(g, x, layer), e,
+                            planes<R>(links, g, MU, opp), nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer));
+        load_link12_pair<R>(c, planes<R>(links, g, NU, par), n, d, planes<R>(links, g, NU, par),
+                            nbr_elem<MU, +1, NU, -1, DLT>(g, x, layer));
         const M3<R> cb = mul_nn(c, b);
         const M3<R> ed = mul_nn(e, d);
-        load_link_pair<R>(a, planes<R>(links, g, NU, opp), nbr_elem<MU, +1, NU, 0, DLT>(g, x, layer), f,
-                          planes<R>(links, g, NU, opp), nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer), g.stride);
+        load_link12_pair<R>(a, planes<R>(links, g, NU, opp), nbr_elem<MU, +1, NU, 0, DLT>(g, x, layer), f,
+                            planes<R>(links, g, NU, opp), nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer));
         acc_nd(A, a, cb);
         acc_dn(A, ed, f);
     }
@@ -148,7 +148,7 @@ __device__ __forceinline__ void update_link(store_t<R> *__restrict__ links, cons
     add_staple<MU, 2, R, DLT>(A, links, g, x, layer, par, n);
     add_staple<MU, 3, R, DLT>(A, links, g, x, layer, par, n);
     store_t<R> *own = planes<R>(links, g, MU, par);
-    M3<R> U = load_link<R>(own, g.stride, n);
+    M3<R> U = load_link12<R>(own, n);
     const uint64_t site = (uint64_t)layer * (uint64_t)(2 * g.Vh) + (uint64_t)lex_of(g, x);
     heatbath<R, HIT1>(U, A, beta, seed, 4 * site + MU, sweep, nhit, att, acc);
     store_link<R>(own, g.stride, n, U);
@@ -311,12 +311,12 @@ __device__ __forceinline__ double plaq_plane(const store_t<R> *__restrict__ link
                                              int layer, int par, int n)
 {
     const int opp = par ^ 1;
-    const M3<double> umu = convert<double>(load_link<R>(planes<R>(links, g, MU, par), g.stride, n));
-    const M3<double> unu_xmu = convert<double>(
-        load_link<R>(planes<R>(links, g, NU, opp), g.stride, nbr_elem<MU, +1, NU, 0, DLT>(g, x, layer)));
-    const M3<double> unu = convert<double>(load_link<R>(planes<R>(links, g, NU, par), g.stride, n));
-    const M3<double> umu_xnu = convert<double>(
-        load_link<R>(planes<R>(links, g, MU, opp), g.stride, nbr_elem<NU, +1, MU, 0, DLT>(g, x, layer)));
+    const M3<double> umu = convert<double>(load_link12<R>(planes<R>(links, g, MU, par), n));
+    const M3<double> unu_xmu =
+        convert<double>(load_link12<R>(planes<R>(links, g, NU, opp), nbr_elem<MU, +1, NU, 0, DLT>(g, x, layer)));
+    const M3<double> unu = convert<double>(load_link12<R>(planes<R>(links, g, NU, par), n));
+    const M3<double> umu_xnu =
+        convert<double>(load_link12<R>(planes<R>(links, g, MU, opp), nbr_elem<NU, +1, MU, 0, DLT>(g, x, layer)));
     const M3<double> P = mul_nn(umu, unu_xmu);
     const M3<double> Q = mul_nn(unu, umu_xnu);
     double s = 0.0;
