@@ -98,6 +98,16 @@ template <typename R> __device__ __forceinline__ R retrace(const M3<R> &A)
     return A.e[0][0].re + A.e[1][1].re + A.e[2][2].re;
 }
 
+// precision-generic device math (FP32 tier: single-precision functions)
+__device__ __forceinline__ double log_r(double x) { return log(x); }
+__device__ __forceinline__ float log_r(float x) { return logf(x); }
+__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+__device__ __forceinline__ float sqrt_r(float x) { return sqrtf(x); }
+__device__ __forceinline__ double cospi_r(double x) { return cospi(x); }
+__device__ __forceinline__ float cospi_r(float x) { return cospif(x); }
+__device__ __forceinline__ void sincospi_r(double x, double *s, double *c) { sincospi(x, s, c); }
+__device__ __forceinline__ void sincospi_r(float x, float *s, float *c) { sincospif(x, s, c); }
+
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11)
 // ---------------------------------------------------------------------------
@@ -376,10 +386,11 @@ __device__ __forceinline__ void reunit(M3<double> &u)
     Cx<double> *r0 = u.e[0], *r1 = u.e[1], *r2 = u.e[2];
     const double n0 = sqrt(r0[0].re * r0[0].re + r0[0].im * r0[0].im + r0[1].re * r0[1].re + r0[1].im * r0[1].im +
                            r0[2].re * r0[2].re + r0[2].im * r0[2].im);
+    const double i0 = 1.0 / n0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        r0[k].re /= n0;
-        r0[k].im /= n0;
+        r0[k].re *= i0;
+        r0[k].im *= i0;
     }
     Cx<double> d{0.0, 0.0};
 #pragma unroll
@@ -391,10 +402,11 @@ __device__ __forceinline__ void reunit(M3<double> &u)
     }
     const double n1 = sqrt(r1[0].re * r1[0].re + r1[0].im * r1[0].im + r1[1].re * r1[1].re + r1[1].im * r1[1].im +
                            r1[2].re * r1[2].re + r1[2].im * r1[2].im);
+    const double i1 = 1.0 / n1;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        r1[k].re /= n1;
-        r1[k].im /= n1;
+        r1[k].re *= i1;
+        r1[k].im *= i1;
     }
     // r2_k = conj(r0_{k+1} r1_{k+2} - r0_{k+2} r1_{k+1})
     (void)r2;

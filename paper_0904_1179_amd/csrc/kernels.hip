@@ -59,45 +59,50 @@ __device__ __forceinline__ void add_staple(M3<R> &A, const store_t<R> *__restric
 //   a0 = 1 - 2 lambda^2, cos(theta) = 2 u5 - 1, phi = 2 pi u6;
 // then rows i, j of U and W are multiplied from the left by r = P(a) P(v/k)
 // with P(p) = [[p0 + i p3, p2 + i p1], [-p2 + i p1, p0 - i p3]].
+// The SU(2) step runs in the link precision R (FP64 links: FP64 throughout,
+// accept decisions in FP64); the uniforms are formed exactly in FP64 first.
+// The link is reunitarised in FP64 at the end.
 // ---------------------------------------------------------------------------
 template <typename R, bool HIT1>
-__device__ __forceinline__ void heatbath(M3<R> &U, const M3<R> &A, double beta, uint64_t seed, uint64_t lid,
+__device__ __forceinline__ void heatbath(M3<R> &U, const M3<R> &A, double beta_d, uint64_t seed, uint64_t lid,
                                          uint64_t sweep, int nhit, int &att, int &acc)
 {
     if (HIT1) nhit = 1;  // 1-hit: a single attempt, no loop
+    const R beta = R(beta_d);
     M3<R> W = mul_nn(U, A);
 #pragma unroll
     for (int sub = 0; sub < 3; ++sub) {
         const int i = (sub == 1) ? 1 : 0;
         const int j = (sub == 0) ? 1 : 2;
-        const double v0 = 0.5 * (double(W.e[i][i].re) + double(W.e[j][j].re));
-        const double v1 = -0.5 * (double(W.e[i][j].im) + double(W.e[j][i].im));
-        const double v2 = 0.5 * (double(W.e[j][i].re) - double(W.e[i][j].re));
-        const double v3 = 0.5 * (double(W.e[j][j].im) - double(W.e[i][i].im));
-        const double k = sqrt(v0 * v0 + v1 * v1 + v2 * v2 + v3 * v3);
-        if (k == 0.0) continue;
-        const double alpha = 2.0 * beta * k / 3.0;
+        const R v0 = R(0.5) * (W.e[i][i].re + W.e[j][j].re);
+        const R v1 = R(-0.5) * (W.e[i][j].im + W.e[j][i].im);
+        const R v2 = R(0.5) * (W.e[j][i].re - W.e[i][j].re);
+        const R v3 = R(0.5) * (W.e[j][j].im - W.e[i][i].im);
+        const R k = sqrt_r(v0 * v0 + v1 * v1 + v2 * v2 + v3 * v3);
+        if (k == R(0)) continue;
+        const R alpha = R(2) * beta * k / R(3);
+        const R inv2alpha = R(1) / (R(2) * alpha);
         bool ok = false;
-        double a0 = 1.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        R a0 = R(1), a1 = R(0), a2 = R(0), a3 = R(0);
         for (int t = 0; t < (HIT1 ? 1 : nhit); ++t) {
             const U64x4 w = philox4x64_10(lid, sweep, ((uint64_t)sub << 32) | (uint64_t)t, kTagHeatbath, seed, 0);
             ++att;
-            const double u1 = unif52(w.w[0]);
-            const double u3 = unif52(w.w[1]);
-            const double u2 = unif32((uint32_t)w.w[2]);
-            const double u4 = unif32((uint32_t)(w.w[2] >> 32));
-            const double c = cos(kTwoPi * u2);
-            const double lam2 = -(log(u1) + c * c * log(u3)) / (2.0 * alpha);
-            if (u4 * u4 <= 1.0 - lam2) {
-                const double u5 = unif32((uint32_t)w.w[3]);
-                const double u6 = unif32((uint32_t)(w.w[3] >> 32));
-                a0 = 1.0 - 2.0 * lam2;
-                const double cth = 2.0 * u5 - 1.0;
-                const double sth = sqrt(1.0 - cth * cth);
-                double sph, cph;
-                sincos(kTwoPi * u6, &sph, &cph);
-                const double rho2 = 1.0 - a0 * a0;
-                const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
+            const R u1 = R(unif52(w.w[0]));
+            const R u3 = R(unif52(w.w[1]));
+            const R u2 = R(unif32((uint32_t)w.w[2]));
+            const R u4 = R(unif32((uint32_t)(w.w[2] >> 32)));
+            const R c = cospi_r(R(2) * u2);
+            const R lam2 = -(log_r(u1) + c * c * log_r(u3)) * inv2alpha;
+            if (u4 * u4 <= R(1) - lam2) {
+                const R u5 = R(unif32((uint32_t)w.w[3]));
+                const R u6 = R(unif32((uint32_t)(w.w[3] >> 32)));
+                a0 = R(1) - R(2) * lam2;
+                const R cth = R(2) * u5 - R(1);
+                const R sth = sqrt_r(R(1) - cth * cth);
+                R sph, cph;
+                sincospi_r(R(2) * u6, &sph, &cph);
+                const R rho2 = R(1) - a0 * a0;
+                const R rho = rho2 > R(0) ? sqrt_r(rho2) : R(0);
                 a1 = rho * sth * cph;
                 a2 = rho * sth * sph;
                 a3 = rho * cth;
@@ -107,13 +112,14 @@ __device__ __forceinline__ void heatbath(M3<R> &U, const M3<R> &A, double beta, 
         }
         if (!ok) continue;
         ++acc;
-        const double b0 = v0 / k, b1 = v1 / k, b2 = v2 / k, b3 = v3 / k;
+        const R rk = R(1) / k;
+        const R b0 = v0 * rk, b1 = v1 * rk, b2 = v2 * rk, b3 = v3 * rk;
         // quaternion product c = a * b  <=>  P(c) = P(a) P(b)
-        const double c0 = a0 * b0 - a1 * b1 - a2 * b2 - a3 * b3;
-        const double c1 = a0 * b1 + b0 * a1 - (a2 * b3 - a3 * b2);
-        const double c2 = a0 * b2 + b0 * a2 - (a3 * b1 - a1 * b3);
-        const double c3 = a0 * b3 + b0 * a3 - (a1 * b2 - a2 * b1);
-        const Cx<R> r00{R(c0), R(c3)}, r01{R(c2), R(c1)}, r10{R(-c2), R(c1)}, r11{R(c0), R(-c3)};
+        const R c0 = a0 * b0 - a1 * b1 - a2 * b2 - a3 * b3;
+        const R c1 = a0 * b1 + b0 * a1 - (a2 * b3 - a3 * b2);
+        const R c2 = a0 * b2 + b0 * a2 - (a3 * b1 - a1 * b3);
+        const R c3 = a0 * b3 + b0 * a3 - (a1 * b2 - a2 * b1);
+        const Cx<R> r00{c0, c3}, r01{c2, c1}, r10{-c2, c1}, r11{c0, -c3};
 #pragma unroll
         for (int col = 0; col < 3; ++col) {
             const Cx<R> ui = U.e[i][col], uj = U.e[j][col];
