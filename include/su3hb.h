@@ -19,8 +19,9 @@
  * Memory ownership: the caller allocates the device buffers (sizes from
  * su3_footprint) and the HIP stream; the library never allocates or frees
  * device memory.  All calls enqueue on the stream given to su3_create and
- * return without waiting, except su3_plaquette, su3_get_links, su3_set_links,
- * su3_counters and su3_profile_read, which synchronise that stream.
+ * return without waiting, except su3_plaquette, su3_sweep_measure, su3_get_links,
+ * su3_set_links, su3_get_link_sample, su3_counters and su3_profile_read, which
+ * synchronise that stream.
  *
  * Errors: every call returns an su3_status; nothing aborts or throws across
  * the ABI.  su3_last_error() gives a thread-local description of the last
@@ -90,6 +91,12 @@ su3_status su3_start(su3_ctx *c, int32_t hot);
  * advances by n; it keys the random numbers, so sweep(a) then sweep(b) equals
  * sweep(a + b) bit for bit.  SU3_ESTATE before su3_start/su3_set_links. */
 su3_status su3_sweep(su3_ctx *c, int32_t n, double beta);
+
+/* n sweeps, each followed by a plaquette measurement, with one stream
+ * synchronisation at the end (per 256 sweeps) instead of one per sweep:
+ * out[k*(1+nlat) + 0] is the mean plaquette after sweep k, out[k*(1+nlat) + 1 + l]
+ * that of layer l (as su3_plaquette).  n_out >= n * (1 + nlat). */
+su3_status su3_sweep_measure(su3_ctx *c, int32_t n, double beta, double *out, size_t n_out);
 
 /* Mean plaquette 1/3 Re Tr U_P: out[0] over the whole lattice, out[1..nlat] per
  * layer (a plaquette belongs to the layer of its base site).  n >= 1 + nlat.

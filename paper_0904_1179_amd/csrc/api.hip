@@ -7,6 +7,7 @@
 // each pass one k_update launch; the sweep index keys the random numbers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -234,14 +235,11 @@ su3_status su3_start(su3_ctx *c, int32_t hot)
     return SU3_OK;
 }
 
-su3_status su3_sweep(su3_ctx *c, int32_t n, double beta)
+namespace {
+
+// enqueue n sweeps (8 pass launches each); arguments already validated
+su3_status enqueue_sweeps(su3_ctx *c, int32_t n, double beta)
 {
-    su3_status st = check_ctx(c);
-    if (st != SU3_OK) return st;
-    if (n < 0) return fail(SU3_EINVAL, "n must be >= 0");
-    if (!std::isfinite(beta) || !(beta > 0.0)) return fail(SU3_EINVAL, "beta must be finite and > 0");
-    st = check_started(c);
-    if (st != SU3_OK) return st;
     for (int32_t s = 0; s < n; ++s) {
         for (int mu = 0; mu < 4; ++mu)
             for (int par = 0; par < 2; ++par) {
@@ -269,6 +267,61 @@ su3_status su3_sweep(su3_ctx *c, int32_t n, double beta)
     }
     return SU3_OK;
 }
+
+su3_status check_sweep_args(su3_ctx *c, int32_t n, double beta)
+{
+    su3_status st = check_ctx(c);
+    if (st != SU3_OK) return st;
+    if (n < 0) return fail(SU3_EINVAL, "n must be >= 0");
+    if (!std::isfinite(beta) || !(beta > 0.0)) return fail(SU3_EINVAL, "beta must be finite and > 0");
+    return check_started(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+su3_status su3_sweep(su3_ctx *c, int32_t n, double beta)
+{
+    su3_status st = check_sweep_args(c, n, beta);
+    if (st != SU3_OK) return st;
+    return enqueue_sweeps(c, n, beta);
+}
+
+su3_status su3_sweep_measure(su3_ctx *c, int32_t n, double beta, double *out, size_t n_out)
+{
+    su3_status st = check_sweep_args(c, n, beta);
+    if (st != SU3_OK) return st;
+    const int w = 1 + c->p.nlat;
+    if (!out && n > 0) return fail(SU3_EINVAL, "out is NULL");
+    if (n_out < (size_t)n * (size_t)w) return fail(SU3_EINVAL, "out must hold n * (1 + nlat) doubles");
+    double *partials = (double *)(c->scratch + kOffPartials);
+    double *slots = (double *)(c->scratch + kOffMeasure);
+    std::vector<double> h((size_t)kMeasureChunk * 4);
+    const double norm = 18.0 * (double)c->V;
+    for (int32_t done = 0; done < n;) {
+        const int32_t m = std::min<int32_t>(kMeasureChunk, n - done);
+        for (int32_t k = 0; k < m; ++k) {
+            st = enqueue_sweeps(c, 1, beta);
+            if (st != SU3_OK) return st;
+            hipError_t e = launch_plaquette(c->p.precision, c->links, c->g, partials, slots + 4 * k, c->stream);
+            if (e != hipSuccess) return hip_fail(e, "plaquette kernels");
+        }
+        hipError_t e = hipMemcpyAsync(h.data(), slots, sizeof(double) * 4 * m, hipMemcpyDeviceToHost, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "measurement copy");
+        e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(e, "measurement sync");
+        for (int32_t k = 0; k < m; ++k) {
+            double *o = out + (size_t)(done + k) * w;
+            o[0] = h[4 * k] / (norm * c->p.nlat);
+            for (int l = 0; l < c->p.nlat; ++l) o[1 + l] = h[4 * k + 1 + l] / norm;
+        }
+        done += m;
+    }
+    return SU3_OK;
+}
+
+}  // extern "C"
 
 su3_status su3_plaquette(su3_ctx *c, double *out, int32_t n)
 {

@@ -19,10 +19,13 @@ const char *last_error();
 
 // scratch layout (bytes): [0, 16*kCounterSlots) heat-bath counter slots (pairs
 // of u64 attempts, accepts); then 256 bytes of plaquette sums; then the
-// plaquette partials
+// per-sweep plaquette sums of su3_sweep_measure (kMeasureChunk sweeps x 4
+// doubles); then the plaquette partials
 constexpr size_t kOffCounters = 0;
 constexpr size_t kOffSums = 16 * (size_t)kCounterSlots;
-constexpr size_t kOffPartials = kOffSums + 256;
+constexpr int kMeasureChunk = 256;
+constexpr size_t kOffMeasure = kOffSums + 256;
+constexpr size_t kOffPartials = kOffMeasure + 32 * (size_t)kMeasureChunk;
 
 su3_status check_params(const su3_params *p);
 Geom make_geom(const su3_params *p);

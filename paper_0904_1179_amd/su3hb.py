@@ -39,6 +39,7 @@ def _load():
         "su3_start": (st, [vp, C.c_int32]),
         "su3_sweep": (st, [vp, C.c_int32, C.c_double]),
         "su3_plaquette": (st, [vp, dp, C.c_int32]),
+        "su3_sweep_measure": (st, [vp, C.c_int32, C.c_double, dp, sz]),
         "su3_reunitarise": (st, [vp]),
         "su3_get_links": (st, [vp, dp, sz]),
         "su3_set_links": (st, [vp, dp, sz]),
@@ -106,6 +107,13 @@ def su3_start(ctx, hot):
 
 def su3_sweep(ctx, n, beta):
     _check(_lib.su3_sweep(ctx, int(n), float(beta)), "su3_sweep")
+
+
+def su3_sweep_measure(ctx, n, beta, nlat):
+    out = np.zeros((int(n), 1 + nlat))
+    _check(_lib.su3_sweep_measure(ctx, int(n), float(beta), out.ctypes.data_as(C.POINTER(C.c_double)), out.size),
+           "su3_sweep_measure")
+    return out
 
 
 def su3_plaquette(ctx, nlat):
@@ -215,6 +223,10 @@ class Lattice:
 
     def plaquette(self):
         return su3_plaquette(self.ctx, self.nlat)
+
+    def sweep_measure(self, n, beta):
+        """n sweeps; returns the (n, 1 + nlat) plaquettes after each sweep."""
+        return su3_sweep_measure(self.ctx, n, beta, self.nlat)
 
     def reunitarise(self):
         su3_reunitarise(self.ctx)

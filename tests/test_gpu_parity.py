@@ -261,3 +261,19 @@ def test_stream_copy_and_profile(hb):
     lat.sweep(2, 5.7)
     ms, n = lat.profile_read()
     assert n == 16 and ms > 0
+
+
+@pytest.mark.parametrize("nlat", [1, 2])
+def test_sweep_measure_matches_sweep_then_plaquette(hb, nlat):
+    L = (4, 4, 6, 4)
+    a = hb.Lattice(L, nlat=nlat, seed=9)
+    b = hb.Lattice(L, nlat=nlat, seed=9)
+    a.start(True)
+    b.start(True)
+    got = a.sweep_measure(300, 5.7)  # crosses the 256-sweep chunk
+    assert got.shape == (300, 1 + nlat)
+    for k in range(300):
+        b.sweep(1, 5.7)
+        if k in (0, 1, 255, 256, 299):
+            assert np.array_equal(got[k], b.plaquette())
+    assert np.array_equal(a.get_links(), b.get_links())
