@@ -230,6 +230,12 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(L, beta)
 
+    # the paper's own figures (CPU wall clock, FP64), as context only
+    out["paper_context"] = {
+        "one_e5405_core_updates_per_s": 4 * 16 ** 4 * 32 / 48.7,  # Table 1: non-MPI, 16^4, 32 sweeps, 48.7 s
+        "cray_xt4_1296_cores_updates_per_s": 4 * 48 ** 4 * 256 / 28.2,  # Table 3: 48^4 PBC, 256 sweeps, 28.2 s
+        "note": "Berg & Wu, Tables 1 and 3: 2 GHz Intel E5405 (g77) and 2.3 GHz Opteron Cray XT4 (PGI), FP64"}
+
     print(json.dumps(out), flush=True)
 
 
