@@ -95,7 +95,13 @@ su3_status su3_sweep(su3_ctx *c, int32_t n, double beta);
 /* n sweeps, each followed by a plaquette measurement, with one stream
  * synchronisation at the end (per 256 sweeps) instead of one per sweep:
  * out[k*(1+nlat) + 0] is the mean plaquette after sweep k, out[k*(1+nlat) + 1 + l]
- * that of layer l (as su3_plaquette).  n_out >= n * (1 + nlat). */
+ * that of layer l (as su3_plaquette).  n_out >= n * (1 + nlat).
+ * On a single torus the last pass of each sweep (mu = 3, odd sites) also sums
+ * Re Tr(U_new A) over its links, which is the sum of the final plaquettes in
+ * the planes (0,3), (1,3), (2,3) (each contains exactly one odd-site link in
+ * direction 3), and one kernel adds the planes (0,1), (0,2), (1,2); the value
+ * equals su3_plaquette's up to rounding (U_new before its final
+ * reunitarisation; products in the link precision, sums in FP64). */
 su3_status su3_sweep_measure(su3_ctx *c, int32_t n, double beta, double *out, size_t n_out);
 
 /* Mean plaquette 1/3 Re Tr U_P: out[0] over the whole lattice, out[1..nlat] per

@@ -100,9 +100,11 @@ size_t link_bytes_of(const su3_params *p, const Geom &g)
     return (size_t)72 * (size_t)g.stride * (p->precision == 64 ? 16u : 8u);
 }
 
+size_t meas_offset(const Geom &g) { return (size_t)round_up(kOffPartials + 8LL * g.nlat * plaq_blocks(g), 256); }
+
 size_t scratch_bytes_of(const Geom &g)
 {
-    return (size_t)round_up(kOffPartials + 8LL * g.nlat * plaq_blocks(g), 256);
+    return (size_t)round_up((long long)meas_offset(g) + 8LL * meas_blocks(g), 256);
 }
 
 }  // namespace su3hb
@@ -237,8 +239,10 @@ su3_status su3_start(su3_ctx *c, int32_t hot)
 
 namespace {
 
-// enqueue n sweeps (8 pass launches each); arguments already validated
-su3_status enqueue_sweeps(su3_ctx *c, int32_t n, double beta)
+// enqueue n sweeps (8 pass launches each); arguments already validated.
+// meas != NULL (single torus only): the last pass of the last sweep also
+// stores its per-workgroup sums of Re Tr(U_new A) there.
+su3_status enqueue_sweeps(su3_ctx *c, int32_t n, double beta, double *meas = nullptr)
 {
     for (int32_t s = 0; s < n; ++s) {
         for (int mu = 0; mu < 4; ++mu)
@@ -253,7 +257,11 @@ su3_status enqueue_sweeps(su3_ctx *c, int32_t n, double beta)
                     hipError_t e = hipEventRecord(c->ev[c->ev_used], c->stream);
                     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
                 }
-                hipError_t e = su3hb::launch_update(c->p.precision, c->links, c->g, mu, par, beta, c->sweep_index,
+                const bool measured = meas && s == n - 1 && mu == 3 && par == 1;
+                hipError_t e =
+                    measured ? su3hb::launch_update_last_measured(c->p.precision, c->links, c->g, beta, c->sweep_index,
+                                                                  c->p.seed, c->p.nhit, counters_of(c), meas, c->stream)
+                             : su3hb::launch_update(c->p.precision, c->links, c->g, mu, par, beta, c->sweep_index,
                                                     c->p.seed, c->p.nhit, counters_of(c), c->stream);
                 if (e != hipSuccess) return hip_fail(e, "update kernel");
                 if (c->profile) {
@@ -302,9 +310,18 @@ su3_status su3_sweep_measure(su3_ctx *c, int32_t n, double beta, double *out, si
     for (int32_t done = 0; done < n;) {
         const int32_t m = std::min<int32_t>(kMeasureChunk, n - done);
         for (int32_t k = 0; k < m; ++k) {
-            st = enqueue_sweeps(c, 1, beta);
-            if (st != SU3_OK) return st;
-            hipError_t e = launch_plaquette(c->p.precision, c->links, c->g, partials, slots + 4 * k, c->stream);
+            hipError_t e;
+            if (c->p.nlat == 1) {
+                // the last pass measures the planes (nu, 3); one kernel adds (0,1), (0,2), (1,2)
+                double *meas = (double *)(c->scratch + meas_offset(c->g));
+                st = enqueue_sweeps(c, 1, beta, meas);
+                if (st != SU3_OK) return st;
+                e = launch_plaquette_rest(c->p.precision, c->links, c->g, partials, meas, slots + 4 * k, c->stream);
+            } else {
+                st = enqueue_sweeps(c, 1, beta);
+                if (st != SU3_OK) return st;
+                e = launch_plaquette(c->p.precision, c->links, c->g, partials, slots + 4 * k, c->stream);
+            }
             if (e != hipSuccess) return hip_fail(e, "plaquette kernels");
         }
         hipError_t e = hipMemcpyAsync(h.data(), slots, sizeof(double) * 4 * m, hipMemcpyDeviceToHost, c->stream);

@@ -63,9 +63,11 @@ __device__ __forceinline__ void add_staple(M3<R> &A, const store_t<R> *__restric
 // accept decisions in FP64); the uniforms are formed exactly in FP64 first.
 // The link is reunitarised in FP64 at the end.
 // ---------------------------------------------------------------------------
+// Returns Re Tr W after the last subgroup, i.e. Re Tr(U_new A) before the
+// final reunitarisation: the sum of the six plaquettes through the new link.
 template <typename R, bool HIT1>
-__device__ __forceinline__ void heatbath(M3<R> &U, const M3<R> &A, double beta_d, uint64_t seed, uint64_t lid,
-                                         uint64_t sweep, int nhit, int &att, int &acc)
+__device__ __forceinline__ double heatbath(M3<R> &U, const M3<R> &A, double beta_d, uint64_t seed, uint64_t lid,
+                                           uint64_t sweep, int nhit, int &att, int &acc)
 {
     if (HIT1) nhit = 1;  // 1-hit: a single attempt, no loop
     const R beta = R(beta_d);
@@ -133,14 +135,15 @@ __device__ __forceinline__ void heatbath(M3<R> &U, const M3<R> &A, double beta_d
     M3<double> Ud = convert<double>(U);
     reunit(Ud);
     U = convert<R>(Ud);
+    return double(W.e[0][0].re) + double(W.e[1][1].re) + double(W.e[2][2].re);
 }
 
 // One thread of a pass: the link U_MU at pass-order position v of its layer
 // (v < nlat * Vh).  Shared by the single-lattice and the batched kernels, so
 // a lattice gets bit-identical updates from both.
 template <int MU, typename R, bool HIT1, bool DLT>
-__device__ __forceinline__ void update_link(store_t<R> *__restrict__ links, const Geom &g, int par, int v, double beta,
-                                            uint64_t sweep, uint64_t seed, int nhit, int &att, int &acc)
+__device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, const Geom &g, int par, int v,
+                                              double beta, uint64_t sweep, uint64_t seed, int nhit, int &att, int &acc)
 {
     const int layer = DLT && v >= g.Vh ? 1 : 0;
     const int i = chunk_order(g, v - layer * g.Vh, g.w2);
@@ -156,8 +159,9 @@ __device__ __forceinline__ void update_link(store_t<R> *__restrict__ links, cons
     store_t<R> *own = planes<R>(links, g, MU, par);
     M3<R> U = load_link12<R>(own, n);
     const uint64_t site = (uint64_t)layer * (uint64_t)(2 * g.Vh) + (uint64_t)lex_of(g, x);
-    heatbath<R, HIT1>(U, A, beta, seed, 4 * site + MU, sweep, nhit, att, acc);
+    const double trw = heatbath<R, HIT1>(U, A, beta, seed, 4 * site + MU, sweep, nhit, att, acc);
     store_link<R>(own, g.stride, n, U);
+    return trw;
 }
 
 // Exact integer heat-bath counts: packed (attempts | accepts << 16) summed
@@ -186,15 +190,39 @@ __device__ __forceinline__ void count_block(int att, int acc, unsigned long long
     }
 }
 
-template <int MU, typename R, bool HIT1, bool DLT>
+// Sum of v over the workgroup, in a fixed order (valid in thread 0).
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double wsum[kBlock / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kBlock / 64; ++w) s += wsum[w];
+    return s;
+}
+
+// One checkerboard pass.  MEAS: also store, per workgroup, the sum of
+// Re Tr(U_new A) over its links (used on the last pass of a sweep, where it
+// is the sum of the final plaquettes in the planes (nu, MU), nu < MU).
+template <int MU, typename R, bool HIT1, bool DLT, bool MEAS = false>
 __global__ __launch_bounds__(kBlock) void k_update(store_t<R> *__restrict__ links, const Geom g, const int par,
                                                    const double beta, const uint64_t sweep, const uint64_t seed,
-                                                   const int nhit, unsigned long long *__restrict__ counters)
+                                                   const int nhit, unsigned long long *__restrict__ counters,
+                                                   double *__restrict__ meas = nullptr)
 {
     const int v = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     int att = 0, acc = 0;
-    if (v < g.nlat * g.Vh) update_link<MU, R, HIT1, DLT>(links, g, par, v, beta, sweep, seed, nhit, att, acc);
+    double trw = 0.0;
+    if (v < g.nlat * g.Vh) trw = update_link<MU, R, HIT1, DLT>(links, g, par, v, beta, sweep, seed, nhit, att, acc);
     count_block(att, acc, counters, blockIdx.x % kCounterSlots);
+    if (MEAS) {
+        __syncthreads();
+        const double b = block_sum(trw);
+        if (threadIdx.x == 0) meas[blockIdx.x] = b;
+    }
 }
 
 // Batched pass: one launch updates the links U_MU of parity `par` of every
@@ -333,20 +361,8 @@ __device__ __forceinline__ double plaq_plane(const store_t<R> *__restrict__ link
     return s;
 }
 
-__device__ __forceinline__ double block_sum(double v)
-{
-    __shared__ double wsum[kBlock / 64];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < kBlock / 64; ++w) s += wsum[w];
-    return s;
-}
-
-template <typename R, bool DLT>
+// ALL: the six planes of the site; otherwise only (0,1), (0,2), (1,2).
+template <typename R, bool DLT, bool ALL>
 __device__ __forceinline__ double plaq_site(const store_t<R> *__restrict__ links, const Geom &g, int layer, int par,
                                            int i)
 {
@@ -355,10 +371,12 @@ __device__ __forceinline__ double plaq_site(const store_t<R> *__restrict__ links
     const int n = layer * g.Vh + i;
     double s = plaq_plane<0, 1, R, DLT>(links, g, x, layer, par, n);
     s += plaq_plane<0, 2, R, DLT>(links, g, x, layer, par, n);
-    s += plaq_plane<0, 3, R, DLT>(links, g, x, layer, par, n);
     s += plaq_plane<1, 2, R, DLT>(links, g, x, layer, par, n);
-    s += plaq_plane<1, 3, R, DLT>(links, g, x, layer, par, n);
-    s += plaq_plane<2, 3, R, DLT>(links, g, x, layer, par, n);
+    if (ALL) {
+        s += plaq_plane<0, 3, R, DLT>(links, g, x, layer, par, n);
+        s += plaq_plane<1, 3, R, DLT>(links, g, x, layer, par, n);
+        s += plaq_plane<2, 3, R, DLT>(links, g, x, layer, par, n);
+    }
     return s;
 }
 
@@ -368,7 +386,7 @@ __device__ __forceinline__ double plaq_site(const store_t<R> *__restrict__ links
 // parities around a chunk are read while they are in that XCD's L2.  Fixed
 // per-thread order, wave shuffles and a fixed per-block order: the sum is
 // bitwise reproducible.
-template <typename R, bool DLT>
+template <typename R, bool DLT, bool ALL = true>
 __global__ __launch_bounds__(kBlock) void k_plaq_partial(const store_t<R> *__restrict__ links, const Geom g,
                                                          const int tiles_per_block, double *__restrict__ partials)
 {
@@ -379,8 +397,8 @@ __global__ __launch_bounds__(kBlock) void k_plaq_partial(const store_t<R> *__res
         const int v = (b * tiles_per_block + t) * kBlock + threadIdx.x;
         if (v < g.Vh) {
             const int i = chunk_order(g, v, g.w2);
-            s += plaq_site<R, DLT>(links, g, layer, 0, i);
-            s += plaq_site<R, DLT>(links, g, layer, 1, i);
+            s += plaq_site<R, DLT, ALL>(links, g, layer, 0, i);
+            s += plaq_site<R, DLT, ALL>(links, g, layer, 1, i);
         }
     }
     const double bs = block_sum(s);
@@ -403,6 +421,20 @@ __global__ __launch_bounds__(kBlock) void k_plaq_final(const double *__restrict_
         }
     }
     if (threadIdx.x == 0) sums[0] = tot;
+}
+
+// single torus: sums[0] = sums[1] = sum of partials a[0..na) + b[0..nb), fixed order
+__global__ __launch_bounds__(kBlock) void k_plaq_final2(const double *__restrict__ a, int na,
+                                                        const double *__restrict__ b, int nb, double *__restrict__ sums)
+{
+    double s = 0.0;
+    for (int k = threadIdx.x; k < na; k += kBlock) s += a[k];
+    for (int k = threadIdx.x; k < nb; k += kBlock) s += b[k];
+    const double r = block_sum(s);
+    if (threadIdx.x == 0) {
+        sums[0] = r;
+        sums[1] = r;
+    }
 }
 
 __global__ void k_zero_u64(unsigned long long *p, int n)
@@ -510,6 +542,44 @@ hipError_t launch_update_batch(int precision, bool hit1, const BatchJob *d_jobs,
         else
             batch_dispatch<float, false>(d_jobs, njobs, ntiles, step, mu, par, s);
     }
+    return hipGetLastError();
+}
+
+template <typename R>
+static void update_meas_launch(store_t<R> *links, const Geom &g, double beta, uint64_t sweep, uint64_t seed, int nhit,
+                               unsigned long long *counters, double *meas, hipStream_t s)
+{
+    const dim3 grid(blocks_for((long long)g.Vh));
+    if (nhit == 1)
+        k_update<3, R, true, false, true><<<grid, kBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit, counters, meas);
+    else
+        k_update<3, R, false, false, true><<<grid, kBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit, counters, meas);
+}
+
+int meas_blocks(const Geom &g) { return (int)blocks_for((long long)g.Vh); }
+
+hipError_t launch_update_last_measured(int precision, void *links, const Geom &g, double beta, uint64_t sweep,
+                                       uint64_t seed, int nhit, unsigned long long *counters, double *meas,
+                                       hipStream_t s)
+{
+    if (precision == 64)
+        update_meas_launch<double>((double2 *)links, g, beta, sweep, seed, nhit, counters, meas, s);
+    else
+        update_meas_launch<float>((float2 *)links, g, beta, sweep, seed, nhit, counters, meas, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_plaquette_rest(int precision, const void *links, const Geom &g, double *partials,
+                                 const double *meas, double *sums, hipStream_t s)
+{
+    const int nblk = plaq_blocks(g);
+    const long long tiles = ((long long)g.Vh + kBlock - 1) / kBlock;
+    const int tpb = (int)((tiles + nblk - 1) / nblk);
+    if (precision == 64)
+        k_plaq_partial<double, false, false><<<nblk, kBlock, 0, s>>>((const double2 *)links, g, tpb, partials);
+    else
+        k_plaq_partial<float, false, false><<<nblk, kBlock, 0, s>>>((const float2 *)links, g, tpb, partials);
+    k_plaq_final2<<<1, kBlock, 0, s>>>(meas, meas_blocks(g), partials, nblk, sums);
     return hipGetLastError();
 }
 

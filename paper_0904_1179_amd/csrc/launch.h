@@ -36,6 +36,15 @@ hipError_t launch_update_batch(int precision, bool hit1, const BatchJob *d_jobs,
                                int mu, int par, hipStream_t s);
 hipError_t launch_plaquette(int precision, const void *links, const Geom &g, double *partials, double *sums,
                             hipStream_t s);
+// Single torus: the last pass of a sweep (mu = 3, odd) that also stores per
+// workgroup the sum of Re Tr(U_new A) into meas[0 .. meas_blocks(g)); then the
+// plaquette sums from those and the planes (0,1), (0,2), (1,2).
+int meas_blocks(const Geom &g);
+hipError_t launch_update_last_measured(int precision, void *links, const Geom &g, double beta, uint64_t sweep,
+                                       uint64_t seed, int nhit, unsigned long long *counters, double *meas,
+                                       hipStream_t s);
+hipError_t launch_plaquette_rest(int precision, const void *links, const Geom &g, double *partials,
+                                 const double *meas, double *sums, hipStream_t s);
 hipError_t launch_reunit(int precision, void *links, const Geom &g, hipStream_t s);
 hipError_t launch_gauge(int precision, void *links, const Geom &g, uint64_t gseed, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
