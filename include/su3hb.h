@@ -104,6 +104,22 @@ su3_status su3_sweep(su3_ctx *c, int32_t n, double beta);
  * reunitarisation; products in the link precision, sums in FP64). */
 su3_status su3_sweep_measure(su3_ctx *c, int32_t n, double beta, double *out, size_t n_out);
 
+/* Double-layered torus only (nlat = 2, else SU3_EINVAL): n sweeps with
+ * per-layer couplings, action S = sum_P beta_{layer(P)} (1 - 1/3 Re Tr U_P)
+ * where a plaquette takes the coupling of the layer of its base site.  The
+ * heat bath samples exp(1/3 Re Tr(U A)) with each staple term weighted by its
+ * plaquette's coupling ("hot" and "cold" layers; the paper leaves the DLT to
+ * be explored, Sec. 1).  Asynchronous, like su3_sweep. */
+su3_status su3_sweep_betas(su3_ctx *c, int32_t n, double beta0, double beta1);
+
+/* Polyakov loops along direction 3: for every start (x0, x1, x2, x3 = 0,
+ * layer) the trace over 3 of the ordered product of U_3 along the closed path
+ * in +3 (2 L3 links when crossing the direction-3 boundary switches the layer,
+ * i.e. flip bit 3 on a double-layered torus).  out[0], out[1] = Re, Im of the
+ * mean over all starts; out[2 + 2l], out[3 + 2l] over the starts in layer l.
+ * n >= 2 (1 + nlat).  Products and sums in FP64.  Synchronises the stream. */
+su3_status su3_polyakov(su3_ctx *c, double *out, int32_t n);
+
 /* Mean plaquette 1/3 Re Tr U_P: out[0] over the whole lattice, out[1..nlat] per
  * layer (a plaquette belongs to the layer of its base site).  n >= 1 + nlat.
  * Accumulated in FP64 with a fixed reduction order (bitwise reproducible).

@@ -45,6 +45,7 @@ static cplx c_mul(cplx a, cplx b)
     return r;
 }
 static cplx c_conj(cplx a) { cplx r = {a.re, -a.im}; return r; }
+static cplx c_scale(cplx a, double s) { cplx r = {a.re * s, a.im * s}; return r; }
 static double c_abs2(cplx a) { return a.re * a.re + a.im * a.im; }
 
 static mat3 m_load(const double *p)
@@ -346,6 +347,47 @@ void su3ref_staple_from_links(const double *nb, double *Aout)
     m_store(&A, Aout);
 }
 
+/* Staple with per-layer couplings (double-layered torus with two betas): the
+ * action is S = sum_P beta_{layer(P)} (1 - 1/3 Re Tr U_P), a plaquette taking
+ * the coupling of the layer of its base site.  The upper staple in plane
+ * (mu,nu) belongs to the plaquette based at x, the lower one to the plaquette
+ * based at x - nu; each enters A with its coupling, and the link weight is
+ * exp(1/3 Re Tr(U A)). */
+static void staple_betas(const su3ref_lattice *lat, int64_t site, int mu, const double beta[2], double *Aout)
+{
+    int64_t lids[18];
+    su3ref_staple_lids(lat, site, mu, lids);
+    mat3 A;
+    memset(&A, 0, sizeof A);
+    int layer_x = (int)(site / lat->V);
+    int j = 0;
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+        const int64_t *q = lids + 6 * j;
+        mat3 a = m_load(lat->links + q[0] * 18), b = m_load(lat->links + q[1] * 18), c = m_load(lat->links + q[2] * 18);
+        mat3 d = m_load(lat->links + q[3] * 18), e = m_load(lat->links + q[4] * 18), f = m_load(lat->links + q[5] * 18);
+        mat3 bd = m_dag(&b), cd = m_dag(&c), dd = m_dag(&d), ed = m_dag(&e);
+        mat3 t = m_mul(&a, &bd);
+        mat3 upper = m_mul(&t, &cd);
+        mat3 u2 = m_mul(&dd, &ed);
+        mat3 lower = m_mul(&u2, &f);
+        int layer_lo = (int)(su3ref_neighbor(lat, site, nu, -1) / lat->V);
+        for (int r = 0; r < 3; ++r)
+            for (int cc = 0; cc < 3; ++cc) {
+                A.m[r][cc] = c_add(A.m[r][cc], c_scale(upper.m[r][cc], beta[layer_x]));
+                A.m[r][cc] = c_add(A.m[r][cc], c_scale(lower.m[r][cc], beta[layer_lo]));
+            }
+        ++j;
+    }
+    m_store(&A, Aout);
+}
+
+void su3ref_staple_betas(const su3ref_lattice *lat, int64_t site, int mu, double beta0, double beta1, double *A)
+{
+    double b[2] = {beta0, beta1};
+    staple_betas(lat, site, mu, b, A);
+}
+
 void su3ref_staple(const su3ref_lattice *lat, int64_t site, int mu, double *A)
 {
     int64_t lids[18];
@@ -560,7 +602,25 @@ static uint64_t splitmix64(uint64_t *s)
 /* U_mu(x) with parity(x) = parity (a checkerboard pass: these links share no  */
 /* plaquette, so they may be updated in any order or at once).  The sweep      */
 /* index s keys the random numbers and continues across calls.                  */
+static void sweep_impl(su3ref_lattice *lat, int n, double beta, const double *betas, int nthreads,
+                       uint64_t order_seed);
+
 void su3ref_sweep(su3ref_lattice *lat, int n, double beta, int nthreads, uint64_t order_seed)
+{
+    sweep_impl(lat, n, beta, NULL, nthreads, order_seed);
+}
+
+/* Sweeps with per-layer couplings beta0 (layer 0) and beta1 (layer 1): the
+ * heat bath samples exp(1/3 Re Tr(U A)) with the weighted staple above, i.e.
+ * the Kennedy-Pendleton strength is alpha = 2k/3 with k from U A. */
+void su3ref_sweep_betas(su3ref_lattice *lat, int n, double beta0, double beta1, int nthreads)
+{
+    double b[2] = {beta0, beta1};
+    sweep_impl(lat, n, 1.0, b, nthreads, 0);
+}
+
+static void sweep_impl(su3ref_lattice *lat, int n, double beta, const double *betas, int nthreads,
+                       uint64_t order_seed)
 {
     int64_t nsites = lat->V * lat->p.nlat;
     /* sites of each parity, in lexicographic order */
@@ -598,7 +658,10 @@ void su3ref_sweep(su3ref_lattice *lat, int n, double beta, int nthreads, uint64_
                 for (int64_t q = 0; q < cnt[par]; ++q) {
                     int64_t site = list[q];
                     double A18[18];
-                    su3ref_staple(lat, site, mu, A18);
+                    if (betas)
+                        staple_betas(lat, site, mu, betas, A18);
+                    else
+                        su3ref_staple(lat, site, mu, A18);
                     mat3 A = m_load(A18);
                     double *up = link_ptr(lat, site, mu);
                     mat3 U = m_load(up);
@@ -644,6 +707,41 @@ void su3ref_plaquette(const su3ref_lattice *lat, double *out)
         tot += sum;
     }
     out[0] = tot / (18.0 * (double)lat->V * nlat);
+}
+
+/* Polyakov loops along direction 3: for every starting site (x0, x1, x2, x3=0,
+ * layer) the trace of the ordered product of U_3 links along the closed path
+ * that steps +3 until it returns to the start -- L3 steps, or 2 L3 if crossing
+ * the direction-3 boundary switches the layer (flip bit 3 on a double-layered
+ * torus).  out[0], out[1] = Re, Im of the mean of Tr/3 over all starting
+ * sites; out[2 + 2l], out[3 + 2l] = the same over the starts in layer l. */
+void su3ref_polyakov(const su3ref_lattice *lat, double *out)
+{
+    const int32_t *L = lat->p.L;
+    int nlat = lat->p.nlat;
+    int64_t V3 = (int64_t)L[0] * L[1] * L[2];
+    double tre = 0, tim = 0;
+    for (int layer = 0; layer < nlat; ++layer) {
+        double sre = 0, sim = 0;
+        for (int64_t s3 = 0; s3 < V3; ++s3) {
+            int64_t start = layer * lat->V + s3; /* x3 = 0 */
+            int64_t x = start;
+            mat3 P = m_identity();
+            do {
+                mat3 u = m_load(link_ptr(lat, x, 3));
+                P = m_mul(&P, &u);
+                x = su3ref_neighbor(lat, x, 3, +1);
+            } while (x != start);
+            sre += (P.m[0][0].re + P.m[1][1].re + P.m[2][2].re) / 3.0;
+            sim += (P.m[0][0].im + P.m[1][1].im + P.m[2][2].im) / 3.0;
+        }
+        out[2 + 2 * layer] = sre / (double)V3;
+        out[3 + 2 * layer] = sim / (double)V3;
+        tre += sre;
+        tim += sim;
+    }
+    out[0] = tre / (double)(V3 * nlat);
+    out[1] = tim / (double)(V3 * nlat);
 }
 
 void su3ref_reunitarise(su3ref_lattice *lat)

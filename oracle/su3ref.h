@@ -63,6 +63,18 @@ void su3ref_plaquette(const su3ref_lattice *lat, double *out);
 
 void su3ref_reunitarise(su3ref_lattice *lat);
 
+/* Double-layered torus with per-layer couplings: a plaquette takes the
+ * coupling of the layer of its base site; n sweeps at beta0 (layer 0) and
+ * beta1 (layer 1). */
+void su3ref_sweep_betas(su3ref_lattice *lat, int n, double beta0, double beta1, int nthreads);
+/* The staple of link (site, mu) with each plaquette term weighted by its coupling. */
+void su3ref_staple_betas(const su3ref_lattice *lat, int64_t site, int mu, double beta0, double beta1, double *A18);
+
+/* Polyakov loops along direction 3 (closed paths; 2 L3 steps when crossing
+ * the direction-3 boundary switches the layer): out[0..1] = Re, Im of the mean
+ * of Tr/3, out[2+2l .. 3+2l] the same per starting layer l. */
+void su3ref_polyakov(const su3ref_lattice *lat, double *out);
+
 uint64_t su3ref_get_sweeps(const su3ref_lattice *lat);
 void su3ref_set_sweeps(su3ref_lattice *lat, uint64_t s);
 void su3ref_counters(const su3ref_lattice *lat, uint64_t *attempts, uint64_t *accepts);

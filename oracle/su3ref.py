@@ -40,6 +40,9 @@ def load():
         "su3ref_sweep": (None, [vp, C.c_int, C.c_double, C.c_int, u64]),
         "su3ref_plaquette": (None, [vp, dp]),
         "su3ref_reunitarise": (None, [vp]),
+        "su3ref_sweep_betas": (None, [vp, C.c_int, C.c_double, C.c_double, C.c_int]),
+        "su3ref_polyakov": (None, [vp, dp]),
+        "su3ref_staple_betas": (None, [vp, i64, C.c_int, C.c_double, C.c_double, dp]),
         "su3ref_get_sweeps": (u64, [vp]),
         "su3ref_set_sweeps": (None, [vp, u64]),
         "su3ref_counters": (None, [vp, C.POINTER(u64), C.POINTER(u64)]),
@@ -206,6 +209,20 @@ class Oracle:
 
     def reunitarise(self):
         _lib.su3ref_reunitarise(self._h)
+
+    def sweep_betas(self, n, beta0, beta1, nthreads=0):
+        _lib.su3ref_sweep_betas(self._h, int(n), float(beta0), float(beta1), int(nthreads))
+
+    def staple_betas(self, site, mu, beta0, beta1):
+        out = np.zeros(18)
+        _lib.su3ref_staple_betas(self._h, int(site), int(mu), float(beta0), float(beta1), _p(out, C.c_double))
+        return to_complex(out)
+
+    def polyakov(self):
+        """Complex mean Polyakov loop (Tr/3): total, then per starting layer."""
+        out = np.zeros(2 + 2 * self.nlat)
+        _lib.su3ref_polyakov(self._h, _p(out, C.c_double))
+        return out[0::2] + 1j * out[1::2]
 
     @property
     def sweeps(self):

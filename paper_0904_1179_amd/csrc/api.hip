@@ -102,9 +102,11 @@ size_t link_bytes_of(const su3_params *p, const Geom &g)
 
 size_t meas_offset(const Geom &g) { return (size_t)round_up(kOffPartials + 8LL * g.nlat * plaq_blocks(g), 256); }
 
+size_t polyakov_offset(const Geom &g) { return (size_t)round_up((long long)meas_offset(g) + 8LL * meas_blocks(g), 256); }
+
 size_t scratch_bytes_of(const Geom &g)
 {
-    return (size_t)round_up((long long)meas_offset(g) + 8LL * meas_blocks(g), 256);
+    return (size_t)round_up((long long)polyakov_offset(g) + 16LL * g.nlat * polyakov_blocks(g), 256);
 }
 
 }  // namespace su3hb
@@ -242,7 +244,7 @@ namespace {
 // enqueue n sweeps (8 pass launches each); arguments already validated.
 // meas != NULL (single torus only): the last pass of the last sweep also
 // stores its per-workgroup sums of Re Tr(U_new A) there.
-su3_status enqueue_sweeps(su3_ctx *c, int32_t n, double beta, double *meas = nullptr)
+su3_status enqueue_sweeps(su3_ctx *c, int32_t n, double beta, double *meas = nullptr, const double *betas = nullptr)
 {
     for (int32_t s = 0; s < n; ++s) {
         for (int mu = 0; mu < 4; ++mu)
@@ -258,11 +260,16 @@ su3_status enqueue_sweeps(su3_ctx *c, int32_t n, double beta, double *meas = nul
                     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
                 }
                 const bool measured = meas && s == n - 1 && mu == 3 && par == 1;
-                hipError_t e =
-                    measured ? su3hb::launch_update_last_measured(c->p.precision, c->links, c->g, beta, c->sweep_index,
-                                                                  c->p.seed, c->p.nhit, counters_of(c), meas, c->stream)
-                             : su3hb::launch_update(c->p.precision, c->links, c->g, mu, par, beta, c->sweep_index,
-                                                    c->p.seed, c->p.nhit, counters_of(c), c->stream);
+                hipError_t e;
+                if (betas)
+                    e = su3hb::launch_update_twob(c->p.precision, c->links, c->g, mu, par, betas[0], betas[1],
+                                                  c->sweep_index, c->p.seed, c->p.nhit, counters_of(c), c->stream);
+                else if (measured)
+                    e = su3hb::launch_update_last_measured(c->p.precision, c->links, c->g, beta, c->sweep_index,
+                                                           c->p.seed, c->p.nhit, counters_of(c), meas, c->stream);
+                else
+                    e = su3hb::launch_update(c->p.precision, c->links, c->g, mu, par, beta, c->sweep_index, c->p.seed,
+                                             c->p.nhit, counters_of(c), c->stream);
                 if (e != hipSuccess) return hip_fail(e, "update kernel");
                 if (c->profile) {
                     e = hipEventRecord(c->ev[c->ev_used + 1], c->stream);
@@ -294,6 +301,45 @@ su3_status su3_sweep(su3_ctx *c, int32_t n, double beta)
     su3_status st = check_sweep_args(c, n, beta);
     if (st != SU3_OK) return st;
     return enqueue_sweeps(c, n, beta);
+}
+
+su3_status su3_sweep_betas(su3_ctx *c, int32_t n, double beta0, double beta1)
+{
+    su3_status st = check_sweep_args(c, n, beta0);
+    if (st != SU3_OK) return st;
+    if (!std::isfinite(beta1) || !(beta1 > 0.0)) return fail(SU3_EINVAL, "beta1 must be finite and > 0");
+    if (c->p.nlat != 2) return fail(SU3_EINVAL, "per-layer couplings need a double-layered torus (nlat = 2)");
+    const double b[2] = {beta0, beta1};
+    return enqueue_sweeps(c, n, 1.0, nullptr, b);
+}
+
+su3_status su3_polyakov(su3_ctx *c, double *out, int32_t n)
+{
+    su3_status st = check_ctx(c);
+    if (st != SU3_OK) return st;
+    if (!out || n < 2 * (1 + c->p.nlat)) return fail(SU3_EINVAL, "out must hold 2 * (1 + nlat) doubles");
+    st = check_started(c);
+    if (st != SU3_OK) return st;
+    double *partials = (double *)(c->scratch + polyakov_offset(c->g));
+    double *sums = (double *)(c->scratch + kOffSums) + 8;
+    hipError_t e = launch_polyakov(c->p.precision, c->links, c->g, partials, sums, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "Polyakov kernels");
+    double h[4] = {0, 0, 0, 0};
+    e = hipMemcpyAsync(h, sums, sizeof(double) * 2 * c->p.nlat, hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "Polyakov copy");
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "Polyakov sync");
+    const double V3 = (double)c->g.L[0] * c->g.L[1] * c->g.L[2];
+    out[0] = out[1] = 0.0;
+    for (int l = 0; l < c->p.nlat; ++l) {
+        out[2 + 2 * l] = h[2 * l] / V3;
+        out[3 + 2 * l] = h[2 * l + 1] / V3;
+        out[0] += h[2 * l];
+        out[1] += h[2 * l + 1];
+    }
+    out[0] /= V3 * c->p.nlat;
+    out[1] /= V3 * c->p.nlat;
+    return SU3_OK;
 }
 
 su3_status su3_sweep_measure(su3_ctx *c, int32_t n, double beta, double *out, size_t n_out)

@@ -85,6 +85,18 @@ template <typename R> __device__ __forceinline__ void set_zero(M3<R> &C)
         for (int b = 0; b < 3; ++b) C.e[a][b] = Cx<R>{R(0), R(0)};
 }
 
+// C += s A
+template <typename R> __device__ __forceinline__ void scale_acc(M3<R> &C, const M3<R> &A, R s)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            C.e[a][b].re += s * A.e[a][b].re;
+            C.e[a][b].im += s * A.e[a][b].im;
+        }
+}
+
 template <typename R> __device__ __forceinline__ M3<R> mul_nn(const M3<R> &A, const M3<R> &B)
 {
     M3<R> C;

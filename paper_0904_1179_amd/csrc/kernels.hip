@@ -30,9 +30,12 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 // (c, d) -- c of thread x is d of thread x + nu - mu; (a, f) -- a of thread x
 // is f of thread x + mu + nu.
 // ---------------------------------------------------------------------------
-template <int MU, int NU, typename R, bool DLT>
+// TWOB (double-layered torus with per-layer couplings wb[0], wb[1]): the upper
+// term belongs to the plaquette based at x, the lower one to the plaquette
+// based at x - nu; each is weighted by the coupling of that base site's layer.
+template <int MU, int NU, typename R, bool DLT, bool TWOB = false>
 __device__ __forceinline__ void add_staple(M3<R> &A, const store_t<R> *__restrict__ links, const Geom &g,
-                                           const int x[4], int layer, int par, int n)
+                                           const int x[4], int layer, int par, int n, const R *wb = nullptr)
 {
     if constexpr (NU != MU) {
         const int opp = par ^ 1;
@@ -43,10 +46,21 @@ __device__ __forceinline__ void add_staple(M3<R> &A, const store_t<R> *__restric
                             nbr_elem<MU, +1, NU, -1, DLT>(g, x, layer));
         const M3<R> cb = mul_nn(c, b);
         const M3<R> ed = mul_nn(e, d);
+        const int elo = nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer);
         load_link12_pair<R>(a, planes<R>(links, g, NU, opp), nbr_elem<MU, +1, NU, 0, DLT>(g, x, layer), f,
-                            planes<R>(links, g, NU, opp), nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer));
-        acc_nd(A, a, cb);
-        acc_dn(A, ed, f);
+                            planes<R>(links, g, NU, opp), elo);
+        if constexpr (TWOB) {
+            M3<R> t;
+            set_zero(t);
+            acc_nd(t, a, cb);
+            scale_acc(A, t, wb[layer]);
+            set_zero(t);
+            acc_dn(t, ed, f);
+            scale_acc(A, t, wb[elo >= g.Vh ? 1 : 0]);
+        } else {
+            acc_nd(A, a, cb);
+            acc_dn(A, ed, f);
+        }
     }
 }
 
@@ -141,9 +155,10 @@ __device__ __forceinline__ double heatbath(M3<R> &U, const M3<R> &A, double beta
 // One thread of a pass: the link U_MU at pass-order position v of its layer
 // (v < nlat * Vh).  Shared by the single-lattice and the batched kernels, so
 // a lattice gets bit-identical updates from both.
-template <int MU, typename R, bool HIT1, bool DLT>
+template <int MU, typename R, bool HIT1, bool DLT, bool TWOB = false>
 __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, const Geom &g, int par, int v,
-                                              double beta, uint64_t sweep, uint64_t seed, int nhit, int &att, int &acc)
+                                              double beta, uint64_t sweep, uint64_t seed, int nhit, int &att, int &acc,
+                                              const R *b = nullptr)
 {
     const int layer = DLT && v >= g.Vh ? 1 : 0;
     const int i = chunk_order(g, v - layer * g.Vh, g.w2);
@@ -152,14 +167,15 @@ __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, co
     site_coords(g, par, i, x);
     M3<R> A;
     set_zero(A);
-    add_staple<MU, 0, R, DLT>(A, links, g, x, layer, par, n);
-    add_staple<MU, 1, R, DLT>(A, links, g, x, layer, par, n);
-    add_staple<MU, 2, R, DLT>(A, links, g, x, layer, par, n);
-    add_staple<MU, 3, R, DLT>(A, links, g, x, layer, par, n);
+    add_staple<MU, 0, R, DLT, TWOB>(A, links, g, x, layer, par, n, b);
+    add_staple<MU, 1, R, DLT, TWOB>(A, links, g, x, layer, par, n, b);
+    add_staple<MU, 2, R, DLT, TWOB>(A, links, g, x, layer, par, n, b);
+    add_staple<MU, 3, R, DLT, TWOB>(A, links, g, x, layer, par, n, b);
     store_t<R> *own = planes<R>(links, g, MU, par);
     M3<R> U = load_link12<R>(own, n);
     const uint64_t site = (uint64_t)layer * (uint64_t)(2 * g.Vh) + (uint64_t)lex_of(g, x);
-    const double trw = heatbath<R, HIT1>(U, A, beta, seed, 4 * site + MU, sweep, nhit, att, acc);
+    // with per-layer couplings the staple carries them: alpha = 2k/3
+    const double trw = heatbath<R, HIT1>(U, A, TWOB ? 1.0 : beta, seed, 4 * site + MU, sweep, nhit, att, acc);
     store_link<R>(own, g.stride, n, U);
     return trw;
 }
@@ -223,6 +239,72 @@ __global__ __launch_bounds__(kBlock) void k_update(store_t<R> *__restrict__ link
         const double b = block_sum(trw);
         if (threadIdx.x == 0) meas[blockIdx.x] = b;
     }
+}
+
+// One pass of a double-layered torus with per-layer couplings beta0, beta1.
+template <int MU, typename R, bool HIT1>
+__global__ __launch_bounds__(kBlock) void k_update_twob(store_t<R> *__restrict__ links, const Geom g, const int par,
+                                                        const double beta0, const double beta1, const uint64_t sweep,
+                                                        const uint64_t seed, const int nhit,
+                                                        unsigned long long *__restrict__ counters)
+{
+    const int v = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const R b[2] = {R(beta0), R(beta1)};
+    int att = 0, acc = 0;
+    if (v < g.nlat * g.Vh)
+        update_link<MU, R, HIT1, true, true>(links, g, par, v, 1.0, sweep, seed, nhit, att, acc, b);
+    count_block(att, acc, counters, blockIdx.x % kCounterSlots);
+}
+
+// Polyakov loops along direction 3: thread (layer, x0, x1, x2) walks the
+// closed path x3 = 0, 1, ... (2 L3 links when crossing the direction-3
+// boundary switches the layer) multiplying U_3 in FP64; partial sums of
+// Re and Im of Tr/3 per workgroup and layer.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_polyakov(const store_t<R> *__restrict__ links, const Geom g,
+                                                     double *__restrict__ partials)
+{
+    const int layer = blockIdx.y;
+    const int V3 = g.L[0] * g.L[1] * g.L[2];
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    double re = 0.0, im = 0.0;
+    if (s < V3) {
+        int y[4] = {s % g.L[0], (s / g.L[0]) % g.L[1], s / (g.L[0] * g.L[1]), 0};
+        int ly = layer;
+        M3<double> P;
+        set_zero(P);
+        P.e[0][0].re = P.e[1][1].re = P.e[2][2].re = 1.0;
+        do {
+            const int lex = lex_of(g, y);
+            const int par = (y[0] + y[1] + y[2] + y[3]) & 1;
+            const M3<double> u = convert<double>(load_link<R>(planes<R>(links, g, 3, par), g.stride, ly * g.Vh + (lex >> 1)));
+            P = mul_nn(P, u);
+            step<3, +1, true>(g, y, ly);
+        } while (y[3] != 0 || ly != layer);
+        re = (P.e[0][0].re + P.e[1][1].re + P.e[2][2].re) / 3.0;
+        im = (P.e[0][0].im + P.e[1][1].im + P.e[2][2].im) / 3.0;
+    }
+    const double br = block_sum(re);
+    __syncthreads();
+    const double bi = block_sum(im);
+    if (threadIdx.x == 0) {
+        partials[2 * (layer * gridDim.x + blockIdx.x)] = br;
+        partials[2 * (layer * gridDim.x + blockIdx.x) + 1] = bi;
+    }
+}
+
+// out[2 l], out[2 l + 1] = sums of Re, Im over the partials of layer l (fixed order)
+__global__ __launch_bounds__(kBlock) void k_polyakov_final(const double *__restrict__ partials, int nblk, int nlat,
+                                                           double *__restrict__ out)
+{
+    for (int l = 0; l < nlat; ++l)
+        for (int c = 0; c < 2; ++c) {
+            double s = 0.0;
+            for (int b = threadIdx.x; b < nblk; b += kBlock) s += partials[2 * (l * nblk + b) + c];
+            const double r = block_sum(s);
+            __syncthreads();
+            if (threadIdx.x == 0) out[2 * l + c] = r;
+        }
 }
 
 // Batched pass: one launch updates the links U_MU of parity `par` of every
@@ -603,6 +685,55 @@ hipError_t launch_plaquette(int precision, const void *links, const Geom &g, dou
             k_plaq_partial<float, false><<<grid, kBlock, 0, s>>>((const float2 *)links, g, tpb, partials);
     }
     k_plaq_final<<<1, kBlock, 0, s>>>(partials, nblk, g.nlat, sums);
+    return hipGetLastError();
+}
+
+template <int MU, typename R>
+static void twob_launch(store_t<R> *links, const Geom &g, int par, double b0, double b1, uint64_t sweep, uint64_t seed,
+                        int nhit, unsigned long long *counters, hipStream_t s)
+{
+    const dim3 grid(blocks_for((long long)g.nlat * g.Vh));
+    if (nhit == 1)
+        k_update_twob<MU, R, true><<<grid, kBlock, 0, s>>>(links, g, par, b0, b1, sweep, seed, nhit, counters);
+    else
+        k_update_twob<MU, R, false><<<grid, kBlock, 0, s>>>(links, g, par, b0, b1, sweep, seed, nhit, counters);
+}
+
+template <typename R>
+static void twob_dispatch(store_t<R> *links, const Geom &g, int mu, int par, double b0, double b1, uint64_t sweep,
+                          uint64_t seed, int nhit, unsigned long long *counters, hipStream_t s)
+{
+    switch (mu) {
+    case 0: twob_launch<0, R>(links, g, par, b0, b1, sweep, seed, nhit, counters, s); break;
+    case 1: twob_launch<1, R>(links, g, par, b0, b1, sweep, seed, nhit, counters, s); break;
+    case 2: twob_launch<2, R>(links, g, par, b0, b1, sweep, seed, nhit, counters, s); break;
+    default: twob_launch<3, R>(links, g, par, b0, b1, sweep, seed, nhit, counters, s); break;
+    }
+}
+
+hipError_t launch_update_twob(int precision, void *links, const Geom &g, int mu, int par, double beta0,
+                              double beta1, uint64_t sweep, uint64_t seed, int nhit, unsigned long long *counters,
+                              hipStream_t s)
+{
+    if (precision == 64)
+        twob_dispatch<double>((double2 *)links, g, mu, par, beta0, beta1, sweep, seed, nhit, counters, s);
+    else
+        twob_dispatch<float>((float2 *)links, g, mu, par, beta0, beta1, sweep, seed, nhit, counters, s);
+    return hipGetLastError();
+}
+
+int polyakov_blocks(const Geom &g) { return (int)blocks_for((long long)g.L[0] * g.L[1] * g.L[2]); }
+
+hipError_t launch_polyakov(int precision, const void *links, const Geom &g, double *partials, double *out,
+                           hipStream_t s)
+{
+    const int nblk = polyakov_blocks(g);
+    const dim3 grid(nblk, g.nlat);
+    if (precision == 64)
+        k_polyakov<double><<<grid, kBlock, 0, s>>>((const double2 *)links, g, partials);
+    else
+        k_polyakov<float><<<grid, kBlock, 0, s>>>((const float2 *)links, g, partials);
+    k_polyakov_final<<<1, kBlock, 0, s>>>(partials, nblk, g.nlat, out);
     return hipGetLastError();
 }
 

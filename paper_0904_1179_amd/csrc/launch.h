@@ -45,6 +45,15 @@ hipError_t launch_update_last_measured(int precision, void *links, const Geom &g
                                        hipStream_t s);
 hipError_t launch_plaquette_rest(int precision, const void *links, const Geom &g, double *partials,
                                  const double *meas, double *sums, hipStream_t s);
+// double-layered torus with per-layer couplings (a plaquette takes its base site's layer coupling)
+hipError_t launch_update_twob(int precision, void *links, const Geom &g, int mu, int par, double beta0,
+                              double beta1, uint64_t sweep, uint64_t seed, int nhit, unsigned long long *counters,
+                              hipStream_t s);
+// Polyakov loops along direction 3: out[2 l], out[2 l + 1] = sums of Re, Im of Tr/3 over the starts in layer l;
+// partials: 2 * nlat * polyakov_blocks(g) doubles
+int polyakov_blocks(const Geom &g);
+hipError_t launch_polyakov(int precision, const void *links, const Geom &g, double *partials, double *out,
+                           hipStream_t s);
 hipError_t launch_reunit(int precision, void *links, const Geom &g, hipStream_t s);
 hipError_t launch_gauge(int precision, void *links, const Geom &g, uint64_t gseed, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);

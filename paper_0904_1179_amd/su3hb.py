@@ -40,6 +40,8 @@ def _load():
         "su3_sweep": (st, [vp, C.c_int32, C.c_double]),
         "su3_plaquette": (st, [vp, dp, C.c_int32]),
         "su3_sweep_measure": (st, [vp, C.c_int32, C.c_double, dp, sz]),
+        "su3_sweep_betas": (st, [vp, C.c_int32, C.c_double, C.c_double]),
+        "su3_polyakov": (st, [vp, dp, C.c_int32]),
         "su3_reunitarise": (st, [vp]),
         "su3_get_links": (st, [vp, dp, sz]),
         "su3_set_links": (st, [vp, dp, sz]),
@@ -114,6 +116,16 @@ def su3_sweep_measure(ctx, n, beta, nlat):
     _check(_lib.su3_sweep_measure(ctx, int(n), float(beta), out.ctypes.data_as(C.POINTER(C.c_double)), out.size),
            "su3_sweep_measure")
     return out
+
+
+def su3_sweep_betas(ctx, n, beta0, beta1):
+    _check(_lib.su3_sweep_betas(ctx, int(n), float(beta0), float(beta1)), "su3_sweep_betas")
+
+
+def su3_polyakov(ctx, nlat):
+    out = np.zeros(2 * (1 + nlat))
+    _check(_lib.su3_polyakov(ctx, out.ctypes.data_as(C.POINTER(C.c_double)), out.size), "su3_polyakov")
+    return out[0::2] + 1j * out[1::2]
 
 
 def su3_plaquette(ctx, nlat):
@@ -223,6 +235,12 @@ class Lattice:
 
     def plaquette(self):
         return su3_plaquette(self.ctx, self.nlat)
+
+    def sweep_betas(self, n, beta0, beta1):
+        su3_sweep_betas(self.ctx, n, beta0, beta1)
+
+    def polyakov(self):
+        return su3_polyakov(self.ctx, self.nlat)
 
     def sweep_measure(self, n, beta):
         """n sweeps; returns the (n, 1 + nlat) plaquettes after each sweep."""

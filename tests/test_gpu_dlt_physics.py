@@ -1,0 +1,58 @@
+"""GPU parity of the double-layered-torus extensions against the oracle:
+sweeps with per-layer couplings and Polyakov loops."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hb():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0904_1179_amd as hb_
+
+    return hb_
+
+
+@pytest.mark.parametrize("L,mask,b0,b1,nhit", [((4, 4, 4, 6), 0x7, 5.5, 6.2, 1), ((6, 4, 4, 4), 0xF, 0.8, 6.0, 1),
+                                               ((4, 4, 4, 4), 0x7, 5.7, 5.7, 2), ((8, 8, 8, 4), 0x7, 6.2, 5.5, 1)])
+def test_two_couplings_match_oracle(hb, L, mask, b0, b1, nhit):
+    from oracle import su3ref
+
+    lat = hb.Lattice(L, nlat=2, flip_mask=mask, seed=31, nhit=nhit)
+    ref = su3ref.Oracle(L, nlat=2, flip_mask=mask, seed=31, nhit=nhit)
+    lat.start(True)
+    ref.start(True)
+    for s in range(2):
+        lat.sweep_betas(1, b0, b1)
+        ref.sweep_betas(1, b0, b1)
+        assert np.abs(lat.get_links() - ref.links()).max() < 1e-12, f"sweep {s + 1}"
+        assert np.abs(lat.plaquette() - ref.plaquette()).max() < 1e-13
+        assert lat.counters()[1:] == ref.counters()
+
+
+def test_two_couplings_rejected_on_single_torus(hb):
+    lat = hb.Lattice(4, seed=1)
+    lat.start(True)
+    with pytest.raises(hb.SU3Error):
+        lat.sweep_betas(1, 5.7, 6.0)
+
+
+@pytest.mark.parametrize("L,nlat,mask,precision", [((4, 4, 4, 6), 1, None, 64), ((4, 6, 4, 4), 2, 0x7, 64),
+                                                   ((4, 4, 4, 4), 2, 0xF, 64), ((8, 8, 8, 8), 1, None, 32)])
+def test_polyakov_matches_oracle(hb, L, nlat, mask, precision):
+    from oracle import su3ref
+
+    lat = hb.Lattice(L, nlat=nlat, flip_mask=mask, seed=17, precision=precision)
+    ref = su3ref.Oracle(L, nlat=nlat, flip_mask=mask, seed=17)
+    lat.start(False)
+    assert np.all(lat.polyakov() == 1.0)
+    lat.start(True)
+    ref.start(True)
+    lat.sweep(2, 5.7)
+    ref.sweep(2, 5.7)
+    tol = 1e-13 if precision == 64 else 1e-5
+    assert np.abs(lat.polyakov() - ref.polyakov()).max() < tol
