@@ -369,6 +369,39 @@ __device__ __forceinline__ void load_link12_pair(M3<R> &p, const store_t<R> *bp,
     rebuild_row2(q);
 }
 
+// Nontemporal access to the link a pass updates: no other thread of the pass
+// reads it, so it should not displace reusable staple links from L2.
+template <typename R> struct NtVec;
+template <> struct NtVec<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct NtVec<float> { typedef float type __attribute__((ext_vector_type(2))); };
+
+template <typename R> __device__ __forceinline__ M3<R> load_link12_nt(const store_t<R> *block, int n)
+{
+    typedef typename NtVec<R>::type V;
+    M3<R> m;
+    const V *p = reinterpret_cast<const V *>(link_at<R>(block, n));
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        const V v = __builtin_nontemporal_load(p + e * kTile);
+        m.e[e / 3][e % 3] = Cx<R>{v.x, v.y};
+    }
+    rebuild_row2(m);
+    return m;
+}
+
+template <typename R> __device__ __forceinline__ void store_link_nt(store_t<R> *block, int n, const M3<R> &m)
+{
+    typedef typename NtVec<R>::type V;
+    V *p = reinterpret_cast<V *>(link_at<R>(block, n));
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        V v;
+        v.x = m.e[e / 3][e % 3].re;
+        v.y = m.e[e / 3][e % 3].im;
+        __builtin_nontemporal_store(v, p + e * kTile);
+    }
+}
+
 template <typename R> __device__ __forceinline__ void store_link(store_t<R> *block, long long, int n, const M3<R> &m)
 {
     store_t<R> *p = link_at<R>(block, n);

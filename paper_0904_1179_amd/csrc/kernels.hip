@@ -172,11 +172,11 @@ __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, co
     add_staple<MU, 2, R, DLT, TWOB>(A, links, g, x, layer, par, n, b);
     add_staple<MU, 3, R, DLT, TWOB>(A, links, g, x, layer, par, n, b);
     store_t<R> *own = planes<R>(links, g, MU, par);
-    M3<R> U = load_link12<R>(own, n);
+    M3<R> U = load_link12_nt<R>(own, n);
     const uint64_t site = (uint64_t)layer * (uint64_t)(2 * g.Vh) + (uint64_t)lex_of(g, x);
     // with per-layer couplings the staple carries them: alpha = 2k/3
     const double trw = heatbath<R, HIT1>(U, A, TWOB ? 1.0 : beta, seed, 4 * site + MU, sweep, nhit, att, acc);
-    store_link<R>(own, g.stride, n, U);
+    store_link_nt<R>(own, n, U);
     return trw;
 }
 
