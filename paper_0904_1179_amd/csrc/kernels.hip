@@ -220,6 +220,17 @@ __device__ __forceinline__ double block_sum(double v)
     return s;
 }
 
+// Tile of this workgroup in a pass of parity `par`.  Every pass reads the
+// whole lattice, and the passes of a sweep alternate in parity, so the odd
+// passes walk the tiles backwards: a pass begins on the links its
+// predecessor read last, which are still in L2 and in the memory-side cache.
+// The order does not change the result, only which links are in cache.
+__device__ __forceinline__ int pass_tile(int par)
+{
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    return par ? (int)gridDim.x - 1 - t : t;
+}
+
 // One checkerboard pass.  MEAS: also store, per workgroup, the sum of
 // Re Tr(U_new A) over its links (used on the last pass of a sweep, where it
 // is the sum of the final plaquettes in the planes (nu, MU), nu < MU).
@@ -229,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_update(store_t<R> *__restrict__ link
                                                    const int nhit, unsigned long long *__restrict__ counters,
                                                    double *__restrict__ meas = nullptr)
 {
-    const int v = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int v = pass_tile(par) * kBlock + threadIdx.x;
     int att = 0, acc = 0;
     double trw = 0.0;
     if (v < g.nlat * g.Vh) trw = update_link<MU, R, HIT1, DLT>(links, g, par, v, beta, sweep, seed, nhit, att, acc);
@@ -248,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_update_twob(store_t<R> *__restrict__
                                                         const uint64_t seed, const int nhit,
                                                         unsigned long long *__restrict__ counters)
 {
-    const int v = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int v = pass_tile(par) * kBlock + threadIdx.x;
     const R b[2] = {R(beta0), R(beta1)};
     int att = 0, acc = 0;
     if (v < g.nlat * g.Vh)
