@@ -102,7 +102,10 @@ size_t link_bytes_of(const su3_params *p, const Geom &g)
 
 size_t meas_offset(const Geom &g) { return (size_t)round_up(kOffPartials + 8LL * g.nlat * plaq_blocks(g), 256); }
 
-size_t polyakov_offset(const Geom &g) { return (size_t)round_up((long long)meas_offset(g) + 8LL * meas_blocks(g), 256); }
+size_t polyakov_offset(const Geom &g)
+{
+    return (size_t)round_up((long long)meas_offset(g) + 3 * 8LL * meas_blocks(g), 256);
+}
 
 size_t scratch_bytes_of(const Geom &g)
 {
@@ -242,8 +245,9 @@ su3_status su3_start(su3_ctx *c, int32_t hot)
 namespace {
 
 // enqueue n sweeps (8 pass launches each); arguments already validated.
-// meas != NULL (single torus only): the last pass of the last sweep also
-// stores its per-workgroup sums of Re Tr(U_new A) there.
+// meas != NULL (single torus only): in the last sweep the odd passes of
+// mu = 1, 2, 3 also store their per-workgroup plaquette sums of the planes
+// (nu, mu), nu < mu, in meas[(mu - 1) * meas_blocks .. mu * meas_blocks).
 su3_status enqueue_sweeps(su3_ctx *c, int32_t n, double beta, double *meas = nullptr, const double *betas = nullptr)
 {
     for (int32_t s = 0; s < n; ++s) {
@@ -259,14 +263,15 @@ su3_status enqueue_sweeps(su3_ctx *c, int32_t n, double beta, double *meas = nul
                     hipError_t e = hipEventRecord(c->ev[c->ev_used], c->stream);
                     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
                 }
-                const bool measured = meas && s == n - 1 && mu == 3 && par == 1;
+                const bool measured = meas && s == n - 1 && mu >= 1 && par == 1;
                 hipError_t e;
                 if (betas)
                     e = su3hb::launch_update_twob(c->p.precision, c->links, c->g, mu, par, betas[0], betas[1],
                                                   c->sweep_index, c->p.seed, c->p.nhit, counters_of(c), c->stream);
                 else if (measured)
-                    e = su3hb::launch_update_last_measured(c->p.precision, c->links, c->g, beta, c->sweep_index,
-                                                           c->p.seed, c->p.nhit, counters_of(c), meas, c->stream);
+                    e = su3hb::launch_update_measured(c->p.precision, c->links, c->g, mu, beta, c->sweep_index,
+                                                      c->p.seed, c->p.nhit, counters_of(c),
+                                                      meas + (size_t)(mu - 1) * su3hb::meas_blocks(c->g), c->stream);
                 else
                     e = su3hb::launch_update(c->p.precision, c->links, c->g, mu, par, beta, c->sweep_index, c->p.seed,
                                              c->p.nhit, counters_of(c), c->stream);
@@ -358,11 +363,11 @@ su3_status su3_sweep_measure(su3_ctx *c, int32_t n, double beta, double *out, si
         for (int32_t k = 0; k < m; ++k) {
             hipError_t e;
             if (c->p.nlat == 1) {
-                // the last pass measures the planes (nu, 3); one kernel adds (0,1), (0,2), (1,2)
+                // the odd passes of mu = 1, 2, 3 measure all six planes; one workgroup adds their partials
                 double *meas = (double *)(c->scratch + meas_offset(c->g));
                 st = enqueue_sweeps(c, 1, beta, meas);
                 if (st != SU3_OK) return st;
-                e = launch_plaquette_rest(c->p.precision, c->links, c->g, partials, meas, slots + 4 * k, c->stream);
+                e = launch_measure_final(meas, c->g, slots + 4 * k, c->stream);
             } else {
                 st = enqueue_sweeps(c, 1, beta);
                 if (st != SU3_OK) return st;

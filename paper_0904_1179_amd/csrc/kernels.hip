@@ -152,31 +152,54 @@ __device__ __forceinline__ double heatbath(M3<R> &U, const M3<R> &A, double beta
     return double(W.e[0][0].re) + double(W.e[1][1].re) + double(W.e[2][2].re);
 }
 
+// Re Tr(u s), accumulated in FP64.
+template <typename R> __device__ __forceinline__ double retr_mul(const M3<R> &u, const M3<R> &s)
+{
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            t += (double)u.e[i][k].re * (double)s.e[k][i].re - (double)u.e[i][k].im * (double)s.e[k][i].im;
+    return t;
+}
+
 // One thread of a pass: the link U_MU at pass-order position v of its layer
 // (v < nlat * Vh).  Shared by the single-lattice and the batched kernels, so
 // a lattice gets bit-identical updates from both.
-template <int MU, typename R, bool HIT1, bool DLT, bool TWOB = false>
+// MEAS: also return Re Tr(U_new S) with S the staple terms of the directions
+// nu < MU.  Summed over the sites of one parity these are all plaquettes of
+// the planes (nu, MU), nu < MU, each once (the upper term of site x is the
+// plaquette based at x, the lower one that based at x - nu).  After the odd
+// pass of MU no later pass of the sweep changes U_nu or U_MU for nu < MU, so
+// the odd passes of MU = 1, 2, 3 together give the final plaquettes of all
+// six planes.  Without MEAS the return value is Re Tr(U_new A) (unused).
+template <int MU, typename R, bool HIT1, bool DLT, bool TWOB = false, bool MEAS = false>
 __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, const Geom &g, int par, int v,
                                               double beta, uint64_t sweep, uint64_t seed, int nhit, int &att, int &acc,
                                               const R *b = nullptr)
 {
+    static_assert(!MEAS || (MU > 0 && !TWOB), "measured passes: MU = 1, 2, 3 with one coupling");
     const int layer = DLT && v >= g.Vh ? 1 : 0;
     const int i = chunk_order(g, v - layer * g.Vh, g.w2);
     const int n = layer * g.Vh + i;
     int x[4];
     site_coords(g, par, i, x);
-    M3<R> A;
+    M3<R> A, S;
     set_zero(A);
     add_staple<MU, 0, R, DLT, TWOB>(A, links, g, x, layer, par, n, b);
+    if constexpr (MEAS && MU == 1) S = A;
     add_staple<MU, 1, R, DLT, TWOB>(A, links, g, x, layer, par, n, b);
+    if constexpr (MEAS && MU == 2) S = A;
     add_staple<MU, 2, R, DLT, TWOB>(A, links, g, x, layer, par, n, b);
     add_staple<MU, 3, R, DLT, TWOB>(A, links, g, x, layer, par, n, b);
     store_t<R> *own = planes<R>(links, g, MU, par);
     M3<R> U = load_link12_nt<R>(own, n);
     const uint64_t site = (uint64_t)layer * (uint64_t)(2 * g.Vh) + (uint64_t)lex_of(g, x);
     // with per-layer couplings the staple carries them: alpha = 2k/3
-    const double trw = heatbath<R, HIT1>(U, A, TWOB ? 1.0 : beta, seed, 4 * site + MU, sweep, nhit, att, acc);
+    double trw = heatbath<R, HIT1>(U, A, TWOB ? 1.0 : beta, seed, 4 * site + MU, sweep, nhit, att, acc);
     store_link_nt<R>(own, n, U);
+    if constexpr (MEAS && MU < 3) trw = retr_mul(U, S);
     return trw;
 }
 
@@ -243,7 +266,8 @@ __global__ __launch_bounds__(kBlock) void k_update(store_t<R> *__restrict__ link
     const int v = pass_tile(par) * kBlock + threadIdx.x;
     int att = 0, acc = 0;
     double trw = 0.0;
-    if (v < g.nlat * g.Vh) trw = update_link<MU, R, HIT1, DLT>(links, g, par, v, beta, sweep, seed, nhit, att, acc);
+    if (v < g.nlat * g.Vh)
+        trw = update_link<MU, R, HIT1, DLT, false, MEAS>(links, g, par, v, beta, sweep, seed, nhit, att, acc);
     count_block(att, acc, counters, blockIdx.x % kCounterSlots);
     if (MEAS) {
         __syncthreads();
@@ -454,8 +478,8 @@ __device__ __forceinline__ double plaq_plane(const store_t<R> *__restrict__ link
     return s;
 }
 
-// ALL: the six planes of the site; otherwise only (0,1), (0,2), (1,2).
-template <typename R, bool DLT, bool ALL>
+// The six planes of the site.
+template <typename R, bool DLT>
 __device__ __forceinline__ double plaq_site(const store_t<R> *__restrict__ links, const Geom &g, int layer, int par,
                                            int i)
 {
@@ -465,11 +489,9 @@ __device__ __forceinline__ double plaq_site(const store_t<R> *__restrict__ links
     double s = plaq_plane<0, 1, R, DLT>(links, g, x, layer, par, n);
     s += plaq_plane<0, 2, R, DLT>(links, g, x, layer, par, n);
     s += plaq_plane<1, 2, R, DLT>(links, g, x, layer, par, n);
-    if (ALL) {
-        s += plaq_plane<0, 3, R, DLT>(links, g, x, layer, par, n);
-        s += plaq_plane<1, 3, R, DLT>(links, g, x, layer, par, n);
-        s += plaq_plane<2, 3, R, DLT>(links, g, x, layer, par, n);
-    }
+    s += plaq_plane<0, 3, R, DLT>(links, g, x, layer, par, n);
+    s += plaq_plane<1, 3, R, DLT>(links, g, x, layer, par, n);
+    s += plaq_plane<2, 3, R, DLT>(links, g, x, layer, par, n);
     return s;
 }
 
@@ -479,7 +501,7 @@ __device__ __forceinline__ double plaq_site(const store_t<R> *__restrict__ links
 // parities around a chunk are read while they are in that XCD's L2.  Fixed
 // per-thread order, wave shuffles and a fixed per-block order: the sum is
 // bitwise reproducible.
-template <typename R, bool DLT, bool ALL = true>
+template <typename R, bool DLT>
 __global__ __launch_bounds__(kBlock) void k_plaq_partial(const store_t<R> *__restrict__ links, const Geom g,
                                                          const int tiles_per_block, double *__restrict__ partials)
 {
@@ -490,8 +512,8 @@ __global__ __launch_bounds__(kBlock) void k_plaq_partial(const store_t<R> *__res
         const int v = (b * tiles_per_block + t) * kBlock + threadIdx.x;
         if (v < g.Vh) {
             const int i = chunk_order(g, v, g.w2);
-            s += plaq_site<R, DLT, ALL>(links, g, layer, 0, i);
-            s += plaq_site<R, DLT, ALL>(links, g, layer, 1, i);
+            s += plaq_site<R, DLT>(links, g, layer, 0, i);
+            s += plaq_site<R, DLT>(links, g, layer, 1, i);
         }
     }
     const double bs = block_sum(s);
@@ -516,13 +538,22 @@ __global__ __launch_bounds__(kBlock) void k_plaq_final(const double *__restrict_
     if (threadIdx.x == 0) sums[0] = tot;
 }
 
-// single torus: sums[0] = sums[1] = sum of partials a[0..na) + b[0..nb), fixed order
-__global__ __launch_bounds__(kBlock) void k_plaq_final2(const double *__restrict__ a, int na,
-                                                        const double *__restrict__ b, int nb, double *__restrict__ sums)
+// single torus: sums[0] = sums[1] = sum of the partials a[0..na), fixed order
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double *__restrict__ a, int na,
+                                                         double *__restrict__ sums)
 {
+    // thread t adds a[t], a[t + kBlock], ... in that order; the loads of
+    // eight terms are issued together
     double s = 0.0;
-    for (int k = threadIdx.x; k < na; k += kBlock) s += a[k];
-    for (int k = threadIdx.x; k < nb; k += kBlock) s += b[k];
+    int k = threadIdx.x;
+    for (; k + 7 * kBlock < na; k += 8 * kBlock) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = a[k + j * kBlock];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += v[j];
+    }
+    for (; k < na; k += kBlock) s += a[k];
     const double r = block_sum(s);
     if (threadIdx.x == 0) {
         sums[0] = r;
@@ -638,41 +669,46 @@ hipError_t launch_update_batch(int precision, bool hit1, const BatchJob *d_jobs,
     return hipGetLastError();
 }
 
-template <typename R>
+template <int MU, typename R>
 static void update_meas_launch(store_t<R> *links, const Geom &g, double beta, uint64_t sweep, uint64_t seed, int nhit,
                                unsigned long long *counters, double *meas, hipStream_t s)
 {
     const dim3 grid(blocks_for((long long)g.Vh));
     if (nhit == 1)
-        k_update<3, R, true, false, true><<<grid, kBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit, counters, meas);
+        k_update<MU, R, true, false, true><<<grid, kBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit, counters,
+                                                                    meas);
     else
-        k_update<3, R, false, false, true><<<grid, kBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit, counters, meas);
+        k_update<MU, R, false, false, true><<<grid, kBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit, counters,
+                                                                     meas);
+}
+
+template <typename R>
+static void update_meas_dispatch(store_t<R> *links, const Geom &g, int mu, double beta, uint64_t sweep,
+                                 uint64_t seed, int nhit, unsigned long long *counters, double *meas, hipStream_t s)
+{
+    switch (mu) {
+    case 1: update_meas_launch<1, R>(links, g, beta, sweep, seed, nhit, counters, meas, s); break;
+    case 2: update_meas_launch<2, R>(links, g, beta, sweep, seed, nhit, counters, meas, s); break;
+    default: update_meas_launch<3, R>(links, g, beta, sweep, seed, nhit, counters, meas, s); break;
+    }
 }
 
 int meas_blocks(const Geom &g) { return (int)blocks_for((long long)g.Vh); }
 
-hipError_t launch_update_last_measured(int precision, void *links, const Geom &g, double beta, uint64_t sweep,
-                                       uint64_t seed, int nhit, unsigned long long *counters, double *meas,
-                                       hipStream_t s)
+hipError_t launch_update_measured(int precision, void *links, const Geom &g, int mu, double beta, uint64_t sweep,
+                                  uint64_t seed, int nhit, unsigned long long *counters, double *meas, hipStream_t s)
 {
+    if (mu < 1 || mu > 3) return hipErrorInvalidValue;
     if (precision == 64)
-        update_meas_launch<double>((double2 *)links, g, beta, sweep, seed, nhit, counters, meas, s);
+        update_meas_dispatch<double>((double2 *)links, g, mu, beta, sweep, seed, nhit, counters, meas, s);
     else
-        update_meas_launch<float>((float2 *)links, g, beta, sweep, seed, nhit, counters, meas, s);
+        update_meas_dispatch<float>((float2 *)links, g, mu, beta, sweep, seed, nhit, counters, meas, s);
     return hipGetLastError();
 }
 
-hipError_t launch_plaquette_rest(int precision, const void *links, const Geom &g, double *partials,
-                                 const double *meas, double *sums, hipStream_t s)
+hipError_t launch_measure_final(const double *meas, const Geom &g, double *sums, hipStream_t s)
 {
-    const int nblk = plaq_blocks(g);
-    const long long tiles = ((long long)g.Vh + kBlock - 1) / kBlock;
-    const int tpb = (int)((tiles + nblk - 1) / nblk);
-    if (precision == 64)
-        k_plaq_partial<double, false, false><<<nblk, kBlock, 0, s>>>((const double2 *)links, g, tpb, partials);
-    else
-        k_plaq_partial<float, false, false><<<nblk, kBlock, 0, s>>>((const float2 *)links, g, tpb, partials);
-    k_plaq_final2<<<1, kBlock, 0, s>>>(meas, meas_blocks(g), partials, nblk, sums);
+    k_sum_partials<<<1, kBlock, 0, s>>>(meas, 3 * meas_blocks(g), sums);
     return hipGetLastError();
 }
 

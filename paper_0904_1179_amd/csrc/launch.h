@@ -36,15 +36,15 @@ hipError_t launch_update_batch(int precision, bool hit1, const BatchJob *d_jobs,
                                int mu, int par, hipStream_t s);
 hipError_t launch_plaquette(int precision, const void *links, const Geom &g, double *partials, double *sums,
                             hipStream_t s);
-// Single torus: the last pass of a sweep (mu = 3, odd) that also stores per
-// workgroup the sum of Re Tr(U_new A) into meas[0 .. meas_blocks(g)); then the
-// plaquette sums from those and the planes (0,1), (0,2), (1,2).
+// Single torus: the odd pass of mu (1, 2 or 3) that also stores, per
+// workgroup, the sum of its final plaquettes in the planes (nu, mu), nu < mu,
+// into meas[0 .. meas_blocks(g)).  With the three passes writing consecutive
+// slices of 3 * meas_blocks(g) doubles, launch_measure_final adds them up into
+// sums[0] = sums[1] (the plaquette sum over all six planes).
 int meas_blocks(const Geom &g);
-hipError_t launch_update_last_measured(int precision, void *links, const Geom &g, double beta, uint64_t sweep,
-                                       uint64_t seed, int nhit, unsigned long long *counters, double *meas,
-                                       hipStream_t s);
-hipError_t launch_plaquette_rest(int precision, const void *links, const Geom &g, double *partials,
-                                 const double *meas, double *sums, hipStream_t s);
+hipError_t launch_update_measured(int precision, void *links, const Geom &g, int mu, double beta, uint64_t sweep,
+                                  uint64_t seed, int nhit, unsigned long long *counters, double *meas, hipStream_t s);
+hipError_t launch_measure_final(const double *meas, const Geom &g, double *sums, hipStream_t s);
 // double-layered torus with per-layer couplings (a plaquette takes its base site's layer coupling)
 hipError_t launch_update_twob(int precision, void *links, const Geom &g, int mu, int par, double beta0,
                               double beta1, uint64_t sweep, uint64_t seed, int nhit, unsigned long long *counters,
