@@ -11,7 +11,8 @@ before the timed region, as the paper excludes it from its timings (Sec. 2).
 
 Also reported on the same JSON line:
   roofline      the heat-bath pass kernel against HBM bandwidth, timed with
-                HIP events around every pass launch on the library's stream
+                HIP events on the library's stream around one pass launch per
+                sweep, rotating through the eight passes of a sweep
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
   fp32          the FP32-link tier on the same workload and its plaquette
                 deviation from the FP64 chain

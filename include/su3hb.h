@@ -157,10 +157,12 @@ su3_status su3_counters(su3_ctx *c, uint64_t *sweeps, uint64_t *kp_attempts, uin
  * drawn from key gseed (a test of gauge invariance; not part of a sweep). */
 su3_status su3_gauge_transform(su3_ctx *c, uint64_t gseed);
 
-/* Per-pass timing: while enabled, every heat-bath pass launch is bracketed by
- * HIP events on the context's stream.  su3_profile_read synchronises and
- * returns the summed pass time in ms and the number of passes timed since the
- * last read (then resets both). */
+/* Per-pass timing: while enabled, one heat-bath pass launch per sweep is
+ * bracketed by HIP events on the context's stream, pass 2 mu + parity of the
+ * sweep with index s when 2 mu + parity = s mod 8, so eight consecutive sweeps
+ * time each of the eight passes once at two event records per sweep.
+ * su3_profile_read synchronises and returns the summed time of the timed
+ * passes in ms and their number since the last read (then resets both). */
 su3_status su3_profile(su3_ctx *c, int32_t enable);
 su3_status su3_profile_read(su3_ctx *c, double *total_ms, uint64_t *passes);
 

@@ -253,7 +253,9 @@ su3_status enqueue_sweeps(su3_ctx *c, int32_t n, double beta, double *meas = nul
     for (int32_t s = 0; s < n; ++s) {
         for (int mu = 0; mu < 4; ++mu)
             for (int par = 0; par < 2; ++par) {
-                if (c->profile) {
+                // one timed pass per sweep, rotating through the eight passes
+                const bool timed = c->profile && (uint64_t)(2 * mu + par) == c->sweep_index % 8;
+                if (timed) {
                     while (c->ev_used + 2 > c->ev.size()) {
                         hipEvent_t ev;
                         hipError_t e = hipEventCreate(&ev);
@@ -276,7 +278,7 @@ su3_status enqueue_sweeps(su3_ctx *c, int32_t n, double beta, double *meas = nul
                     e = su3hb::launch_update(c->p.precision, c->links, c->g, mu, par, beta, c->sweep_index, c->p.seed,
                                              c->p.nhit, counters_of(c), c->stream);
                 if (e != hipSuccess) return hip_fail(e, "update kernel");
-                if (c->profile) {
+                if (timed) {
                     e = hipEventRecord(c->ev[c->ev_used + 1], c->stream);
                     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
                     c->ev_used += 2;

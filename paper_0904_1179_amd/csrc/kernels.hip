@@ -1,11 +1,11 @@
 // kernels.hip -- gfx950 kernels of the checkerboard SU(3) heat bath.
 //
-// Link storage (structure of arrays): 72 component planes, plane index
-// (dir * 2 + parity) * 9 + (3 * row + col), each plane `stride` complex
-// numbers (double2 or float2); the link U_dir(x) of site x = (layer, parity, i)
-// is element n = layer * Vh + i of its 9 planes.  A wave of 64 consecutive
-// links therefore reads 64 consecutive complex numbers per plane (1 KiB in
-// FP64): every global access is a fully coalesced 16-byte (8-byte) vector load.
+// Link storage: the links of one (direction, parity) form a block of tiles of
+// 16 consecutive links, each tile holding the 9 complex entries entry-major
+// (double2 or float2); see link_at.  The link U_dir(x) of site
+// x = (layer, parity, i) is element n = layer * Vh + i of block (dir, parity).
+// Sixteen lanes with consecutive n read 16 consecutive complex numbers per
+// entry: whole 128-byte lines, fully coalesced vector loads.
 //
 // The hot kernel is k_update<MU, R>: one checkerboard pass, i.e. every link
 // U_MU(x) with parity(x) = par, one thread per link.  It gathers the 18
@@ -26,41 +26,38 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 // staple: A += U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+ + U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)
 // written as a (c b)^+ + (e d)^+ f with
 //   a = U_nu(x+mu), b = U_mu(x+nu), c = U_nu(x), d = U_nu(x+mu-nu), e = U_mu(x-nu), f = U_nu(x-nu)
-// Pairs loaded together: (b, e) -- b of thread x is e of thread x + 2 nu;
-// (c, d) -- c of thread x is d of thread x + nu - mu; (a, f) -- a of thread x
-// is f of thread x + mu + nu.
+// b and e come from the caller (see update_link); the pairs (c, d) and (a, f)
+// are loaded together: c of thread x is d of thread x + nu - mu, a of thread
+// x is f of thread x + mu + nu.
 // ---------------------------------------------------------------------------
 // TWOB (double-layered torus with per-layer couplings wb[0], wb[1]): the upper
 // term belongs to the plaquette based at x, the lower one to the plaquette
 // based at x - nu; each is weighted by the coupling of that base site's layer.
 template <int MU, int NU, typename R, bool DLT, bool TWOB = false>
-__device__ __forceinline__ void add_staple(M3<R> &A, const store_t<R> *__restrict__ links, const Geom &g,
-                                           const int x[4], int layer, int par, int n, const R *wb = nullptr)
+__device__ __forceinline__ void add_staple(M3<R> &A, const M3<R> &b, const M3<R> &e,
+                                           const store_t<R> *__restrict__ links, const Geom &g, const int x[4],
+                                           int layer, int par, int n, const R *wb = nullptr)
 {
-    if constexpr (NU != MU) {
-        const int opp = par ^ 1;
-        M3<R> b, e, c, d, a, f;
-        load_link12_pair<R>(b, planes<R>(links, g, MU, opp), nbr_elem<NU, +1, MU, 0, DLT>(g, x, layer), e,
-                            planes<R>(links, g, MU, opp), nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer));
-        load_link12_pair<R>(c, planes<R>(links, g, NU, par), n, d, planes<R>(links, g, NU, par),
-                            nbr_elem<MU, +1, NU, -1, DLT>(g, x, layer));
-        const M3<R> cb = mul_nn(c, b);
-        const M3<R> ed = mul_nn(e, d);
-        const int elo = nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer);
-        load_link12_pair<R>(a, planes<R>(links, g, NU, opp), nbr_elem<MU, +1, NU, 0, DLT>(g, x, layer), f,
-                            planes<R>(links, g, NU, opp), elo);
-        if constexpr (TWOB) {
-            M3<R> t;
-            set_zero(t);
-            acc_nd(t, a, cb);
-            scale_acc(A, t, wb[layer]);
-            set_zero(t);
-            acc_dn(t, ed, f);
-            scale_acc(A, t, wb[elo >= g.Vh ? 1 : 0]);
-        } else {
-            acc_nd(A, a, cb);
-            acc_dn(A, ed, f);
-        }
+    const int opp = par ^ 1;
+    M3<R> c, d, a, f;
+    load_link12_pair<R>(c, planes<R>(links, g, NU, par), n, d, planes<R>(links, g, NU, par),
+                        nbr_elem<MU, +1, NU, -1, DLT>(g, x, layer));
+    const M3<R> cb = mul_nn(c, b);
+    const M3<R> ed = mul_nn(e, d);
+    const int elo = nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer);
+    load_link12_pair<R>(a, planes<R>(links, g, NU, opp), nbr_elem<MU, +1, NU, 0, DLT>(g, x, layer), f,
+                        planes<R>(links, g, NU, opp), elo);
+    if constexpr (TWOB) {
+        M3<R> t;
+        set_zero(t);
+        acc_nd(t, a, cb);
+        scale_acc(A, t, wb[layer]);
+        set_zero(t);
+        acc_dn(t, ed, f);
+        scale_acc(A, t, wb[elo >= g.Vh ? 1 : 0]);
+    } else {
+        acc_nd(A, a, cb);
+        acc_dn(A, ed, f);
     }
 }
 
@@ -167,6 +164,20 @@ template <typename R> __device__ __forceinline__ double retr_mul(const M3<R> &u,
 // One thread of a pass: the link U_MU at pass-order position v of its layer
 // (v < nlat * Vh).  Shared by the single-lattice and the batched kernels, so
 // a lattice gets bit-identical updates from both.
+//
+// Load order (single torus).  The six links U_MU(x +- nu) (b and e of the
+// three staple directions) are links of the other parity that the
+// neighbouring sites read in all three direction phases; loaded phase by
+// phase, their lines leave L2 between phases.  They are all loaded first,
+// entry by entry: b and e of the first direction stay in registers for its
+// phase, b and e of the second and b of the third wait in this thread's slots
+// of `stash` (3 * 6 * kBlock entries of LDS, slot-major, so the 64 lanes of a
+// wave access consecutive entries), e of the third stays in registers.  This
+// order is used where kStashOrder holds; otherwise (FP32, whose pass is
+// bound by instruction issue, and the double-layered torus, where six
+// layer-dependent addresses at once would spill) b and e are loaded in their
+// direction's phase and `stash` is unused.
+//
 // MEAS: also return Re Tr(U_new S) with S the staple terms of the directions
 // nu < MU.  Summed over the sites of one parity these are all plaquettes of
 // the planes (nu, MU), nu < MU, each once (the upper term of site x is the
@@ -174,12 +185,56 @@ template <typename R> __device__ __forceinline__ double retr_mul(const M3<R> &u,
 // pass of MU no later pass of the sweep changes U_nu or U_MU for nu < MU, so
 // the odd passes of MU = 1, 2, 3 together give the final plaquettes of all
 // six planes.  Without MEAS the return value is Re Tr(U_new A) (unused).
+constexpr int kStashSlots = 3;
+// Waves per SIMD the pass kernels are compiled for: register budgets of 256
+// (FP64) and 128 (FP32) VGPRs; the stash (3 * 6 * kBlock entries: 72 KiB in
+// FP64, 36 KiB in FP32 per workgroup) fits the 160 KiB of LDS at these
+// occupancies.
+template <typename R> constexpr int kPassWaves = sizeof(R) == 8 ? 2 : 4;
+// The stash order pays where a pass is limited by memory traffic: FP64 on a
+// single torus.  The FP32 pass is limited by instruction issue (FP32 and
+// FP64 vector operations issue at the same rate), so it keeps the
+// direction-by-direction order, as does the double-layered torus.
+template <typename R, bool DLT> constexpr bool kStashOrder = !DLT && sizeof(R) == 8;
+template <typename R> struct Raw12 {
+    store_t<R> v[6];  // rows 0 and 1 as stored
+};
+template <typename R> __device__ __forceinline__ M3<R> from_raw(const Raw12<R> &r)
+{
+    M3<R> m;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) m.e[e / 3][e % 3] = Cx<R>{r.v[e].x, r.v[e].y};
+    rebuild_row2(m);
+    return m;
+}
+// The stash round trip must stay in LDS (kept in registers it would cost
+// the occupancy it is meant to preserve): stash_fence() between the writes
+// and the reads is a compiler-only memory barrier, so the compiler can
+// neither forward the written values nor drop the writes.
+template <typename R> __device__ __forceinline__ void stash_put(store_t<R> *stash, int slot, const Raw12<R> &r)
+{
+#pragma unroll
+    for (int e = 0; e < 6; ++e) stash[(slot * 6 + e) * kBlock + threadIdx.x] = r.v[e];
+}
+template <typename R> __device__ __forceinline__ M3<R> stash_get(const store_t<R> *stash, int slot)
+{
+    Raw12<R> r;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) r.v[e] = stash[(slot * 6 + e) * kBlock + threadIdx.x];
+    return from_raw(r);
+}
+__device__ __forceinline__ void stash_fence() { __asm__ __volatile__("" ::: "memory"); }
+
 template <int MU, typename R, bool HIT1, bool DLT, bool TWOB = false, bool MEAS = false>
 __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, const Geom &g, int par, int v,
                                               double beta, uint64_t sweep, uint64_t seed, int nhit, int &att, int &acc,
-                                              const R *b = nullptr)
+                                              store_t<R> *stash, const R *wb = nullptr)
 {
     static_assert(!MEAS || (MU > 0 && !TWOB), "measured passes: MU = 1, 2, 3 with one coupling");
+    // the staple directions nu != MU in increasing order
+    constexpr int N0 = MU == 0 ? 1 : 0;
+    constexpr int N1 = MU <= 1 ? 2 : 1;
+    constexpr int N2 = MU <= 2 ? 3 : 2;
     const int layer = DLT && v >= g.Vh ? 1 : 0;
     const int i = chunk_order(g, v - layer * g.Vh, g.w2);
     const int n = layer * g.Vh + i;
@@ -187,12 +242,52 @@ __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, co
     site_coords(g, par, i, x);
     M3<R> A, S;
     set_zero(A);
-    add_staple<MU, 0, R, DLT, TWOB>(A, links, g, x, layer, par, n, b);
-    if constexpr (MEAS && MU == 1) S = A;
-    add_staple<MU, 1, R, DLT, TWOB>(A, links, g, x, layer, par, n, b);
-    if constexpr (MEAS && MU == 2) S = A;
-    add_staple<MU, 2, R, DLT, TWOB>(A, links, g, x, layer, par, n, b);
-    add_staple<MU, 3, R, DLT, TWOB>(A, links, g, x, layer, par, n, b);
+    if constexpr (!kStashOrder<R, DLT>) {
+        // b and e of each direction loaded in its phase
+        const store_t<R> *umu = planes<R>(links, g, MU, par ^ 1);
+        M3<R> b, e;
+        load_link12_pair<R>(b, umu, nbr_elem<N0, +1, MU, 0, DLT>(g, x, layer), e, umu,
+                            nbr_elem<N0, -1, MU, 0, DLT>(g, x, layer));
+        add_staple<MU, N0, R, DLT, TWOB>(A, b, e, links, g, x, layer, par, n, wb);
+        if constexpr (MEAS && MU == 1) S = A;
+        load_link12_pair<R>(b, umu, nbr_elem<N1, +1, MU, 0, DLT>(g, x, layer), e, umu,
+                            nbr_elem<N1, -1, MU, 0, DLT>(g, x, layer));
+        add_staple<MU, N1, R, DLT, TWOB>(A, b, e, links, g, x, layer, par, n, wb);
+        if constexpr (MEAS && MU == 2) S = A;
+        load_link12_pair<R>(b, umu, nbr_elem<N2, +1, MU, 0, DLT>(g, x, layer), e, umu,
+                            nbr_elem<N2, -1, MU, 0, DLT>(g, x, layer));
+        add_staple<MU, N2, R, DLT, TWOB>(A, b, e, links, g, x, layer, par, n, wb);
+    } else {
+        Raw12<R> b0, e0, b1, e1, b2, e2;
+        {
+            const store_t<R> *umu = planes<R>(links, g, MU, par ^ 1);
+            const store_t<R> *pb0 = link_at<R>(umu, nbr_elem<N0, +1, MU, 0, false>(g, x, layer));
+            const store_t<R> *pe0 = link_at<R>(umu, nbr_elem<N0, -1, MU, 0, false>(g, x, layer));
+            const store_t<R> *pb1 = link_at<R>(umu, nbr_elem<N1, +1, MU, 0, false>(g, x, layer));
+            const store_t<R> *pe1 = link_at<R>(umu, nbr_elem<N1, -1, MU, 0, false>(g, x, layer));
+            const store_t<R> *pb2 = link_at<R>(umu, nbr_elem<N2, +1, MU, 0, false>(g, x, layer));
+            const store_t<R> *pe2 = link_at<R>(umu, nbr_elem<N2, -1, MU, 0, false>(g, x, layer));
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                b0.v[e] = pb0[e * kTile];
+                e0.v[e] = pe0[e * kTile];
+                b1.v[e] = pb1[e * kTile];
+                e1.v[e] = pe1[e * kTile];
+                b2.v[e] = pb2[e * kTile];
+                e2.v[e] = pe2[e * kTile];
+            }
+        }
+        stash_put<R>(stash, 0, b1);
+        stash_put<R>(stash, 1, e1);
+        stash_put<R>(stash, 2, b2);
+        stash_fence();
+        add_staple<MU, N0, R, DLT, TWOB>(A, from_raw(b0), from_raw(e0), links, g, x, layer, par, n, wb);
+        if constexpr (MEAS && MU == 1) S = A;
+        add_staple<MU, N1, R, DLT, TWOB>(A, stash_get<R>(stash, 0), stash_get<R>(stash, 1), links, g, x, layer, par,
+                                         n, wb);
+        if constexpr (MEAS && MU == 2) S = A;
+        add_staple<MU, N2, R, DLT, TWOB>(A, stash_get<R>(stash, 2), from_raw(e2), links, g, x, layer, par, n, wb);
+    }
     store_t<R> *own = planes<R>(links, g, MU, par);
     M3<R> U = load_link12_nt<R>(own, n);
     const uint64_t site = (uint64_t)layer * (uint64_t)(2 * g.Vh) + (uint64_t)lex_of(g, x);
@@ -258,16 +353,21 @@ __device__ __forceinline__ int pass_tile(int par)
 // Re Tr(U_new A) over its links (used on the last pass of a sweep, where it
 // is the sum of the final plaquettes in the planes (nu, MU), nu < MU).
 template <int MU, typename R, bool HIT1, bool DLT, bool MEAS = false>
-__global__ __launch_bounds__(kBlock) void k_update(store_t<R> *__restrict__ links, const Geom g, const int par,
+__global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update(store_t<R> *__restrict__ links, const Geom g, const int par,
                                                    const double beta, const uint64_t sweep, const uint64_t seed,
                                                    const int nhit, unsigned long long *__restrict__ counters,
                                                    double *__restrict__ meas = nullptr)
 {
+    store_t<R> *st = nullptr;
+    if constexpr (kStashOrder<R, DLT>) {
+        __shared__ store_t<R> stash[kStashSlots * 6 * kBlock];
+        st = stash;
+    }
     const int v = pass_tile(par) * kBlock + threadIdx.x;
     int att = 0, acc = 0;
     double trw = 0.0;
     if (v < g.nlat * g.Vh)
-        trw = update_link<MU, R, HIT1, DLT, false, MEAS>(links, g, par, v, beta, sweep, seed, nhit, att, acc);
+        trw = update_link<MU, R, HIT1, DLT, false, MEAS>(links, g, par, v, beta, sweep, seed, nhit, att, acc, st);
     count_block(att, acc, counters, blockIdx.x % kCounterSlots);
     if (MEAS) {
         __syncthreads();
@@ -278,7 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_update(store_t<R> *__restrict__ link
 
 // One pass of a double-layered torus with per-layer couplings beta0, beta1.
 template <int MU, typename R, bool HIT1>
-__global__ __launch_bounds__(kBlock) void k_update_twob(store_t<R> *__restrict__ links, const Geom g, const int par,
+__global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update_twob(store_t<R> *__restrict__ links, const Geom g, const int par,
                                                         const double beta0, const double beta1, const uint64_t sweep,
                                                         const uint64_t seed, const int nhit,
                                                         unsigned long long *__restrict__ counters)
@@ -287,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_update_twob(store_t<R> *__restrict__
     const R b[2] = {R(beta0), R(beta1)};
     int att = 0, acc = 0;
     if (v < g.nlat * g.Vh)
-        update_link<MU, R, HIT1, true, true>(links, g, par, v, 1.0, sweep, seed, nhit, att, acc, b);
+        update_link<MU, R, HIT1, true, true>(links, g, par, v, 1.0, sweep, seed, nhit, att, acc, nullptr, b);
     count_block(att, acc, counters, blockIdx.x % kCounterSlots);
 }
 
@@ -346,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_polyakov_final(const double *__restr
 // job in `jobs` (sorted by tile_begin).  Workgroup b belongs to the job whose
 // tile range holds b; job j is at sweep index sweep0 + (step - admit_step).
 template <int MU, typename R, bool HIT1>
-__global__ __launch_bounds__(kBlock) void k_update_batch(const BatchJob *__restrict__ jobs, const int njobs,
+__global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update_batch(const BatchJob *__restrict__ jobs, const int njobs,
                                                          const long long step, const int par)
 {
     __shared__ int sj;
@@ -368,7 +468,8 @@ __global__ __launch_bounds__(kBlock) void k_update_batch(const BatchJob *__restr
     const uint64_t sweep = J.sweep0 + (uint64_t)(step - J.admit_step);
     int att = 0, acc = 0;
     if (v < J.g.nlat * J.g.Vh)
-        update_link<MU, R, HIT1, true>((store_t<R> *)J.links, J.g, par, v, J.beta, sweep, J.seed, J.nhit, att, acc);
+        update_link<MU, R, HIT1, true>((store_t<R> *)J.links, J.g, par, v, J.beta, sweep, J.seed, J.nhit, att, acc,
+                                       nullptr);
     count_block(att, acc, J.counters, local % kCounterSlots);
 }
 

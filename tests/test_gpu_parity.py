@@ -258,9 +258,11 @@ def test_stream_copy_and_profile(hb):
     lat = hb.Lattice(8, seed=1)
     lat.start(True)
     lat.profile(True)
-    lat.sweep(2, 5.7)
+    lat.sweep(9, 5.7)
     ms, n = lat.profile_read()
-    assert n == 16 and ms > 0
+    assert n == 9 and ms > 0  # one timed pass per sweep
+    ms, n = lat.profile_read()
+    assert n == 0 and ms == 0
 
 
 @pytest.mark.parametrize("nlat", [1, 2])
