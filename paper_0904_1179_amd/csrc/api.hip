@@ -92,6 +92,11 @@ Geom make_geom(const su3_params *p)
     g.w2 = 1;
     for (int w = 1; w <= p->L[2] / 8; ++w)
         if (p->L[2] % w == 0) g.w2 = w;
+    g.dl0h = su3hb::make_fastdiv((uint32_t)(p->L[0] / 2));
+    g.dl1 = su3hb::make_fastdiv((uint32_t)p->L[1]);
+    g.dl2 = su3hb::make_fastdiv((uint32_t)p->L[2]);
+    g.dl3 = su3hb::make_fastdiv((uint32_t)p->L[3]);
+    g.dw2 = su3hb::make_fastdiv((uint32_t)g.w2);
     return g;
 }
 

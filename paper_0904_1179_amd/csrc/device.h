@@ -111,14 +111,114 @@ template <typename R> __device__ __forceinline__ R retrace(const M3<R> &A)
 }
 
 // precision-generic device math (FP32 tier: single-precision functions)
-__device__ __forceinline__ double log_r(double x) { return log(x); }
+// ---------------------------------------------------------------------------
+// FP64 elementary functions on the argument ranges of the heat bath.  The
+// general library versions handle every input (signs, infinities, huge
+// arguments) and cost 70-100 instructions each; the heat bath only takes
+// logarithms of uniforms in (0, 1] and sines/cosines of pi t with t in [0, 2].
+// Both below are short series with exact coefficients, accurate to about an
+// ulp over those ranges.
+// ---------------------------------------------------------------------------
+
+// ln x for 0 < x <= 1 (normal numbers): x = 2^k m with m in [1/sqrt 2, sqrt 2),
+// ln m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...) with s = (m - 1)/(m + 1),
+// |s| <= 0.1716; ten terms leave a truncation below 1e-17 relative.  ln 2 is
+// split into a 40-bit head (k * head is exact) and the rounded remainder.
+__host__ __device__ inline double log_unit(double x)
+{
+    constexpr double kLn2Hi = 0x1.62e42fefa2000p-1;
+    constexpr double kLn2Lo = 0x1.9ef35793c7673p-41;
+    constexpr double kSqrtHalf = 0x1.6a09e667f3bcdp-1;
+    int k;
+    double m = frexp(x, &k);  // m in [1/2, 1)
+    if (m < kSqrtHalf) {
+        m += m;
+        --k;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double p = 1.0 / 19.0;
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    const double s2 = s + s;
+    const double lnm = fma(s2 * z, p, s2);  // 2 s (1 + z p)
+    const double dk = (double)k;
+    return fma(dk, kLn2Hi, fma(dk, kLn2Lo, lnm));
+}
+
+// sin(pi r), cos(pi r) for |r| <= 1/4 from their Taylor series in y = r^2:
+// coefficients (-1)^j pi^(2j+1)/(2j+1)! (sine, j = 0..8) and
+// (-1)^j pi^(2j)/(2j)! (cosine, j = 0..9); the first omitted terms are below
+// 1e-17 at |pi r| = pi/4.
+__host__ __device__ inline void sincospi_quarter(double r, double *sn, double *cs)
+{
+    const double y = r * r;
+    double ps = 7.952054001475513e-07;
+    ps = fma(ps, y, -2.1915353447830217e-05);
+    ps = fma(ps, y, 0.00046630280576761255);
+    ps = fma(ps, y, -0.0073704309457143504);
+    ps = fma(ps, y, 0.08214588661112823);
+    ps = fma(ps, y, -0.5992645293207921);
+    ps = fma(ps, y, 2.5501640398773455);
+    ps = fma(ps, y, -5.16771278004997);
+    ps = fma(ps, y, 3.141592653589793);
+    double pc = -1.3878952462213771e-07;
+    pc = fma(pc, y, 4.303069587032947e-06);
+    pc = fma(pc, y, -0.0001046381049248457);
+    pc = fma(pc, y, 0.0019295743094039231);
+    pc = fma(pc, y, -0.02580689139001406);
+    pc = fma(pc, y, 0.2353306303588932);
+    pc = fma(pc, y, -1.3352627688545895);
+    pc = fma(pc, y, 4.0587121264167685);
+    pc = fma(pc, y, -4.934802200544679);
+    *sn = r * ps;
+    *cs = fma(pc, y, 1.0);
+}
+
+// t in [0, 2]: q = nearest integer to 2t, r = t - q/2 (exact, |r| <= 1/4),
+// pi t = pi r + q pi/2.
+__host__ __device__ inline void sincospi_0to2(double t, double *sn, double *cs)
+{
+    const double q = rint(t + t);
+    const double r = fma(q, -0.5, t);
+    double s, c;
+    sincospi_quarter(r, &s, &c);
+    const int iq = (int)q & 3;
+    const double ss = (iq & 1) ? c : s, cc = (iq & 1) ? s : c;
+    *sn = (iq & 2) ? -ss : ss;
+    *cs = (iq == 1 || iq == 2) ? -cc : cc;
+}
+
+// cos^2(pi t) for t in [0, 2]: only the parity of the quadrant matters.
+__host__ __device__ inline double cospi_sq_0to2(double t)
+{
+    const double q = rint(t + t);
+    const double r = fma(q, -0.5, t);
+    double s, c;
+    sincospi_quarter(r, &s, &c);
+    return ((int)q & 1) ? s * s : c * c;
+}
+
+// Precision-generic helpers of the heat bath.  FP64: the functions above
+// (arguments: uniforms in (0, 1] and t in [0, 2]); FP32: the library ones.
+__device__ __forceinline__ double log_r(double x) { return log_unit(x); }
 __device__ __forceinline__ float log_r(float x) { return logf(x); }
 __device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
 __device__ __forceinline__ float sqrt_r(float x) { return sqrtf(x); }
-__device__ __forceinline__ double cospi_r(double x) { return cospi(x); }
-__device__ __forceinline__ float cospi_r(float x) { return cospif(x); }
-__device__ __forceinline__ void sincospi_r(double x, double *s, double *c) { sincospi(x, s, c); }
-__device__ __forceinline__ void sincospi_r(float x, float *s, float *c) { sincospif(x, s, c); }
+__device__ __forceinline__ double cospi_sq_r(double t) { return cospi_sq_0to2(t); }
+__device__ __forceinline__ float cospi_sq_r(float t)
+{
+    const float c = cospif(t);
+    return c * c;
+}
+__device__ __forceinline__ void sincospi_r(double t, double *s, double *c) { sincospi_0to2(t, s, c); }
+__device__ __forceinline__ void sincospi_r(float t, float *s, float *c) { sincospif(t, s, c); }
 
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11)
@@ -177,6 +277,33 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
 // lex = x0 + L0 (x1 + L1 (x2 + L2 x3)); with L0 even, the two sites sharing
 // lex >> 1 have opposite parity.  Within a component plane the element of
 // site (layer, parity, i) is n = layer * Vh + i.
+// Unsigned division by a divisor fixed for a launch (Granlund and Montgomery,
+// "Division by invariant integers using multiplication", 1994): with
+// l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1, s1 = min(l, 1),
+// s2 = max(l - 1, 0) and t = floor(m x / 2^32),
+//   floor(x / d) = (t + ((x - t) >> s1)) >> s2   for every 0 <= x < 2^32,
+// a multiply-high and three shifts/adds instead of a division sequence.
+struct FastDiv {
+    uint32_t d, m, s1, s2;
+};
+inline FastDiv make_fastdiv(uint32_t d)
+{
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    FastDiv f;
+    f.d = d;
+    f.m = (uint32_t)((((uint64_t)1 << 32) * ((1ull << l) - d)) / d + 1);
+    f.s1 = l < 1 ? l : 1;
+    f.s2 = l > 1 ? l - 1 : 0;
+    return f;
+}
+__host__ __device__ __forceinline__ int div_by(int x, const FastDiv &f)
+{
+    const uint32_t ux = (uint32_t)x;
+    const uint32_t t = (uint32_t)(((uint64_t)f.m * ux) >> 32);
+    return (int)((t + ((ux - t) >> f.s1)) >> f.s2);
+}
+
 struct Geom {
     int L[4];
     int Vh;             // V / 2
@@ -184,18 +311,19 @@ struct Geom {
     unsigned flip;      // layer-switch mask, 0 on a single torus
     long long stride;   // links per (direction, parity) block (>= nlat * Vh, multiple of 64)
     int w2;             // chunk width of the pass order (divides L2)
+    FastDiv dl0h, dl1, dl2, dl3, dw2;  // division by L0/2, L1, L2, L3, w2
 };
 
 // Coordinates of the site with parity `par` and half-index i.
 __device__ __forceinline__ void site_coords(const Geom &g, int par, int i, int x[4])
 {
     const int l0h = g.L[0] >> 1;
-    int r = i / l0h;
+    int r = div_by(i, g.dl0h);
     const int x0h = i - r * l0h;
-    int q = r / g.L[1];
+    int q = div_by(r, g.dl1);
     x[1] = r - q * g.L[1];
     r = q;
-    q = r / g.L[2];
+    q = div_by(r, g.dl2);
     x[2] = r - q * g.L[2];
     x[3] = q;
     x[0] = 2 * x0h + ((par + x[1] + x[2] + x[3]) & 1);
@@ -247,18 +375,18 @@ __device__ __forceinline__ int nbr_elem(const Geom &g, const int x[4], int layer
 // each XCD owns whole chunks, so a link is re-read while it is still in that
 // XCD's L2.  Lanes of a wave still cover consecutive x0, so loads stay
 // coalesced.  w2 must divide L2.
-__device__ __forceinline__ int chunk_order(const Geom &g, int v, int w2)
+__device__ __forceinline__ int chunk_order(const Geom &g, int v)
 {
-    const int l0h = g.L[0] >> 1;
-    int r = v / l0h;
+    const int l0h = g.L[0] >> 1, w2 = g.w2;
+    int r = div_by(v, g.dl0h);
     const int x0h = v - r * l0h;
-    int q = r / g.L[1];
+    int q = div_by(r, g.dl1);
     const int x1 = r - q * g.L[1];
     r = q;
-    q = r / w2;
+    q = div_by(r, g.dw2);
     const int x2p = r - q * w2;
     r = q;
-    q = r / g.L[3];
+    q = div_by(r, g.dl3);
     const int x3 = r - q * g.L[3];
     const int x2 = q * w2 + x2p;
     return x0h + l0h * (x1 + g.L[1] * (x2 + g.L[2] * x3));

@@ -81,7 +81,8 @@ __device__ __forceinline__ double heatbath(M3<R> &U, const M3<R> &A, double beta
                                            uint64_t sweep, int nhit, int &att, int &acc)
 {
     if (HIT1) nhit = 1;  // 1-hit: a single attempt, no loop
-    const R beta = R(beta_d);
+    // 1/(2 alpha) = 3/(4 beta k): one division per link and 1/k per subgroup
+    const R q34b = R(0.75) / R(beta_d);
     M3<R> W = mul_nn(U, A);
 #pragma unroll
     for (int sub = 0; sub < 3; ++sub) {
@@ -93,8 +94,8 @@ __device__ __forceinline__ double heatbath(M3<R> &U, const M3<R> &A, double beta
         const R v3 = R(0.5) * (W.e[j][j].im - W.e[i][i].im);
         const R k = sqrt_r(v0 * v0 + v1 * v1 + v2 * v2 + v3 * v3);
         if (k == R(0)) continue;
-        const R alpha = R(2) * beta * k / R(3);
-        const R inv2alpha = R(1) / (R(2) * alpha);
+        const R rk = R(1) / k;
+        const R inv2alpha = q34b * rk;
         bool ok = false;
         R a0 = R(1), a1 = R(0), a2 = R(0), a3 = R(0);
         for (int t = 0; t < (HIT1 ? 1 : nhit); ++t) {
@@ -104,8 +105,8 @@ __device__ __forceinline__ double heatbath(M3<R> &U, const M3<R> &A, double beta
             const R u3 = R(unif52(w.w[1]));
             const R u2 = R(unif32((uint32_t)w.w[2]));
             const R u4 = R(unif32((uint32_t)(w.w[2] >> 32)));
-            const R c = cospi_r(R(2) * u2);
-            const R lam2 = -(log_r(u1) + c * c * log_r(u3)) * inv2alpha;
+            const R c2 = cospi_sq_r(R(2) * u2);
+            const R lam2 = -(log_r(u1) + c2 * log_r(u3)) * inv2alpha;
             if (u4 * u4 <= R(1) - lam2) {
                 const R u5 = R(unif32((uint32_t)w.w[3]));
                 const R u6 = R(unif32((uint32_t)(w.w[3] >> 32)));
@@ -125,7 +126,6 @@ __device__ __forceinline__ double heatbath(M3<R> &U, const M3<R> &A, double beta
         }
         if (!ok) continue;
         ++acc;
-        const R rk = R(1) / k;
         const R b0 = v0 * rk, b1 = v1 * rk, b2 = v2 * rk, b3 = v3 * rk;
         // quaternion product c = a * b  <=>  P(c) = P(a) P(b)
         const R c0 = a0 * b0 - a1 * b1 - a2 * b2 - a3 * b3;
@@ -236,7 +236,7 @@ __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, co
     constexpr int N1 = MU <= 1 ? 2 : 1;
     constexpr int N2 = MU <= 2 ? 3 : 2;
     const int layer = DLT && v >= g.Vh ? 1 : 0;
-    const int i = chunk_order(g, v - layer * g.Vh, g.w2);
+    const int i = chunk_order(g, v - layer * g.Vh);
     const int n = layer * g.Vh + i;
     int x[4];
     site_coords(g, par, i, x);
@@ -612,7 +612,7 @@ __global__ __launch_bounds__(kBlock) void k_plaq_partial(const store_t<R> *__res
     for (int t = 0; t < tiles_per_block; ++t) {
         const int v = (b * tiles_per_block + t) * kBlock + threadIdx.x;
         if (v < g.Vh) {
-            const int i = chunk_order(g, v, g.w2);
+            const int i = chunk_order(g, v);
             s += plaq_site<R, DLT>(links, g, layer, 0, i);
             s += plaq_site<R, DLT>(links, g, layer, 1, i);
         }
