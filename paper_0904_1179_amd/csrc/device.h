@@ -464,6 +464,52 @@ template <typename R> __device__ __forceinline__ void rebuild_row2(M3<R> &u)
     }
 }
 
+// Products of SU(3) matrices.  A product is again in SU(3), so only its rows
+// 0 and 1 are formed (18 complex multiply-adds instead of 27) and row 2 is
+// rebuilt from them; the left factor's row 2 is never read.
+// A B
+template <typename R> __device__ __forceinline__ M3<R> mul_nn_su3(const M3<R> &A, const M3<R> &B)
+{
+    M3<R> C;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            Cx<R> t = cmul(A.e[a][0], B.e[0][b]);
+            t = cmadd(t, A.e[a][1], B.e[1][b]);
+            C.e[a][b] = cmadd(t, A.e[a][2], B.e[2][b]);
+        }
+    rebuild_row2(C);
+    return C;
+}
+// A B^+
+template <typename R> __device__ __forceinline__ M3<R> mul_nd_su3(const M3<R> &A, const M3<R> &B)
+{
+    M3<R> C;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            Cx<R> t{R(0), R(0)};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) t = cmadd_nc(t, A.e[a][k], B.e[b][k]);
+            C.e[a][b] = t;
+        }
+    rebuild_row2(C);
+    return C;
+}
+// C += A
+template <typename R> __device__ __forceinline__ void add_to(M3<R> &C, const M3<R> &A)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            C.e[a][b].re += A.e[a][b].re;
+            C.e[a][b].im += A.e[a][b].im;
+        }
+}
+
 // Reads of links produced by this library: only rows 0 and 1 (6 of the 9
 // entries, 2/3 of the bytes) are loaded and row 2 is rebuilt.  Every stored
 // link was reunitarised with the same row-2 formula, so the rebuilt row

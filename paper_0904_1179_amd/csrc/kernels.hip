@@ -42,21 +42,22 @@ __device__ __forceinline__ void add_staple(M3<R> &A, const M3<R> &b, const M3<R>
     M3<R> c, d, a, f;
     load_link12_pair<R>(c, planes<R>(links, g, NU, par), n, d, planes<R>(links, g, NU, par),
                         nbr_elem<MU, +1, NU, -1, DLT>(g, x, layer));
-    const M3<R> cb = mul_nn(c, b);
-    const M3<R> ed = mul_nn(e, d);
+    // c b, e d and a (c b)^+ are SU(3) products: rows 0 and 1 formed, row 2
+    // rebuilt (so the third rows of c, e and a are never needed)
+    const M3<R> cb = mul_nn_su3(c, b);
+    const M3<R> ed = mul_nn_su3(e, d);
     const int elo = nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer);
     load_link12_pair<R>(a, planes<R>(links, g, NU, opp), nbr_elem<MU, +1, NU, 0, DLT>(g, x, layer), f,
                         planes<R>(links, g, NU, opp), elo);
+    const M3<R> up = mul_nd_su3(a, cb);
     if constexpr (TWOB) {
+        scale_acc(A, up, wb[layer]);
         M3<R> t;
-        set_zero(t);
-        acc_nd(t, a, cb);
-        scale_acc(A, t, wb[layer]);
         set_zero(t);
         acc_dn(t, ed, f);
         scale_acc(A, t, wb[elo >= g.Vh ? 1 : 0]);
     } else {
-        acc_nd(A, a, cb);
+        add_to(A, up);
         acc_dn(A, ed, f);
     }
 }

@@ -1,12 +1,14 @@
 """GPU tests of the workload configurations and of the FP32 tier against the
 FP64 oracle.
 
-FP32 tier: links stored and multiplied in FP32; heat-bath scalars,
-reunitarisation, plaquette products and sums in FP64.  Its error against the
-FP64 oracle is stated per result: plaquette relative error <= 1e-5 over the
-first sweeps from the same start (FP32 rounding of the links is ~6e-8 and
-grows slowly along the chain), and agreement of long-run averages within the
-statistical error once the two chains have decorrelated.
+FP32 tier: links stored and multiplied in FP32 and the SU(2) heat-bath step
+taken in FP32 (its uniforms formed exactly in FP64 first); reunitarisation,
+plaquette products and sums in FP64.  Its error against the FP64 oracle is
+stated per result: plaquette relative error <= 1e-5 over the first sweeps from
+the same start (FP32 rounding of the links is ~6e-8 and grows slowly along the
+chain) until an accept/reject decision taken in FP32 goes the other way, and
+agreement of long-run averages within the statistical error once the two
+chains have decorrelated.
 """
 import os
 import sys
