@@ -33,8 +33,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 REAL_BYTES = {64: 8, 32: 4}
 # Algorithmic bytes of one link update in a pass: the pass reads every link of
 # the lattice once (8 reads per updated link) and writes the updated link.
-# Reads take rows 0 and 1 (12 reals; row 2 is rebuilt), writes all 18 reals.
-READ_REALS, WRITE_REALS, READS_PER_UPDATE = 12, 18, 8
+# A link is stored and moved as its rows 0 and 1 (12 reals; row 2 is rebuilt).
+READ_REALS, WRITE_REALS, READS_PER_UPDATE = 12, 12, 8
 
 
 def bytes_per_update(precision):

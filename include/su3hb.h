@@ -16,6 +16,10 @@
  * sweep index, subgroup/attempt, purpose), so a result does not depend on the
  * launch configuration, and resuming from a checkpoint is exact.
  *
+ * Storage: the device keeps rows 0 and 1 of every link (12 reals); row 2 of an
+ * SU(3) matrix is conj(row 0 x row 1) and is rebuilt wherever a link is read,
+ * on the device and in the host copies below.
+ *
  * Memory ownership: the caller allocates the device buffers (sizes from
  * su3_footprint) and the HIP stream; the library never allocates or frees
  * device memory.  All calls enqueue on the stream given to su3_create and
@@ -134,13 +138,17 @@ su3_status su3_reunitarise(su3_ctx *c);
 /* Copy the links to / from host memory in the canonical FP64 layout
  * host[(4*site + mu)*18 + (3*row + col)*2 + reim], site = layer*V + lex,
  * lex = x0 + L0*(x1 + L1*(x2 + L2*x3)).  n_doubles must be 72*V*nlat.
- * For precision 32 the values are widened / rounded to FP32.  Synchronise the
+ * For precision 32 the values are widened / rounded to FP32.  su3_get_links
+ * returns row 2 rebuilt in FP64 from the stored rows 0 and 1; su3_set_links
+ * stores rows 0 and 1 and ignores row 2 (exact for SU(3) input; other input
+ * is thereby read as rows 0, 1 and conj(row 0 x row 1)).  Synchronise the
  * stream.  su3_set_links also marks the context started. */
 su3_status su3_get_links(su3_ctx *c, double *host, size_t n_doubles);
 su3_status su3_set_links(su3_ctx *c, const double *host, size_t n_doubles);
 
 /* Copy the n links with canonical ids lids[k] = 4*site + mu (site as above) to
- * host[18*k .. 18*k+17], same element order as su3_get_links: a sampled check
+ * host[18*k .. 18*k+17], same element order and row-2 rebuild as
+ * su3_get_links: a sampled check
  * of a lattice too large to copy whole.  SU3_EINVAL for an id out of range.
  * Synchronises the stream. */
 su3_status su3_get_link_sample(su3_ctx *c, const uint64_t *lids, size_t n, double *host);

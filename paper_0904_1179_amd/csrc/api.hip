@@ -102,7 +102,8 @@ Geom make_geom(const su3_params *p)
 
 size_t link_bytes_of(const su3_params *p, const Geom &g)
 {
-    return (size_t)72 * (size_t)g.stride * (p->precision == 64 ? 16u : 8u);
+    // 8 (direction, parity) blocks of `stride` links, 6 complex entries each
+    return (size_t)8 * su3hb::kEntries * (size_t)g.stride * (p->precision == 64 ? 16u : 8u);
 }
 
 size_t meas_offset(const Geom &g) { return (size_t)round_up(kOffPartials + 8LL * g.nlat * plaq_blocks(g), 256); }
@@ -138,9 +139,27 @@ su3_status check_started(su3_ctx *c)
 unsigned long long *counters_of(su3_ctx *c) { return (unsigned long long *)(c->scratch + kOffCounters); }
 
 // device element index of entry e of link n of block (dir, par), in complex numbers
+// 18 reals of a link in the host layout (row-major, re/im): row 2 from rows 0
+// and 1 as conj(row 0 x row 1), the formula the kernels use
+void rebuild_row2_host(double *m)
+{
+    for (int k = 0; k < 3; ++k) {
+        const int a = (k + 1) % 3, b = (k + 2) % 3;
+        const double p_re = m[2 * a] * m[6 + 2 * b] - m[2 * a + 1] * m[6 + 2 * b + 1];
+        const double p_im = m[2 * a] * m[6 + 2 * b + 1] + m[2 * a + 1] * m[6 + 2 * b];
+        const double q_re = m[2 * b] * m[6 + 2 * a] - m[2 * b + 1] * m[6 + 2 * a + 1];
+        const double q_im = m[2 * b] * m[6 + 2 * a + 1] + m[2 * b + 1] * m[6 + 2 * a];
+        m[12 + 2 * k] = p_re - q_re;
+        m[12 + 2 * k + 1] = -(p_im - q_im);
+    }
+}
+
 size_t dev_index(const Geom &g, int dir, int par, int e, long long n)
 {
-    return (size_t)(dir * 2 + par) * (size_t)g.stride * 9 + (size_t)(n >> 4) * 144 + (size_t)e * 16 + (size_t)(n & 15);
+    using su3hb::kEntries;
+    using su3hb::kTile;
+    return (size_t)(dir * 2 + par) * (size_t)g.stride * kEntries + (size_t)(n >> 4) * (kEntries * kTile) +
+           (size_t)e * kTile + (size_t)(n & (kTile - 1));
 }
 
 // canonical host index of the plane element (dir, par, e, n): maps (layer, parity, i) to site
@@ -470,7 +489,7 @@ su3_status su3_get_links(su3_ctx *c, double *host, size_t n_doubles)
             site_of_elem(g, par, n, &site);
             for (int dir = 0; dir < 4; ++dir) {
                 double *dst = host + (size_t)(4 * site + dir) * 18;
-                for (int el = 0; el < 9; ++el) {
+                for (int el = 0; el < su3hb::kEntries; ++el) {
                     const size_t idx = dev_index(g, dir, par, el, n);
                     if (c->p.precision == 64) {
                         const double *v = (const double *)buf.data() + 2 * idx;
@@ -482,6 +501,7 @@ su3_status su3_get_links(su3_ctx *c, double *host, size_t n_doubles)
                         dst[2 * el + 1] = (double)v[1];
                     }
                 }
+                rebuild_row2_host(dst);
             }
         }
     return SU3_OK;
@@ -509,7 +529,7 @@ su3_status su3_set_links(su3_ctx *c, const double *host, size_t n_doubles)
             site_of_elem(g, par, n, &site);
             for (int dir = 0; dir < 4; ++dir) {
                 const double *src = host + (size_t)(4 * site + dir) * 18;
-                for (int el = 0; el < 9; ++el) {
+                for (int el = 0; el < su3hb::kEntries; ++el) {
                     const size_t idx = dev_index(g, dir, par, el, n);
                     if (c->p.precision == 64) {
                         double *v = (double *)buf.data() + 2 * idx;
@@ -548,7 +568,7 @@ su3_status su3_get_link_sample(su3_ctx *c, const uint64_t *lids, size_t n, doubl
     const size_t esz = c->p.precision == 64 ? 16 : 8;
     std::vector<unsigned char> buf;
     try {
-        buf.resize(n * 9 * esz);
+        buf.resize(n * su3hb::kEntries * esz);
     } catch (...) {
         return fail(SU3_EINVAL, "out of host memory for the sample");
     }
@@ -565,23 +585,29 @@ su3_status su3_get_link_sample(su3_ctx *c, const uint64_t *lids, size_t n, doubl
         }
         const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
         const size_t elem = (size_t)layer * (size_t)g.Vh + (size_t)((site % c->V) >> 1);
-        for (int el = 0; el < 9; ++el) {
+        for (int el = 0; el < su3hb::kEntries; ++el) {
             const size_t idx = dev_index(g, dir, par, el, (long long)elem);
-            hipError_t e = hipMemcpyAsync(buf.data() + (k * 9 + el) * esz, (const unsigned char *)c->links + idx * esz,
-                                          esz, hipMemcpyDeviceToHost, c->stream);
+            hipError_t e = hipMemcpyAsync(buf.data() + (k * su3hb::kEntries + el) * esz,
+                                          (const unsigned char *)c->links + idx * esz, esz, hipMemcpyDeviceToHost,
+                                          c->stream);
             if (e != hipSuccess) return hip_fail(e, "sample copy");
         }
     }
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "sample sync");
-    for (size_t k = 0; k < n * 9; ++k) {
-        if (c->p.precision == 64) {
-            host[2 * k] = ((const double *)buf.data())[2 * k];
-            host[2 * k + 1] = ((const double *)buf.data())[2 * k + 1];
-        } else {
-            host[2 * k] = (double)((const float *)buf.data())[2 * k];
-            host[2 * k + 1] = (double)((const float *)buf.data())[2 * k + 1];
+    for (size_t k = 0; k < n; ++k) {
+        double *dst = host + 18 * k;
+        for (int el = 0; el < su3hb::kEntries; ++el) {
+            const size_t i = k * su3hb::kEntries + el;
+            if (c->p.precision == 64) {
+                dst[2 * el] = ((const double *)buf.data())[2 * i];
+                dst[2 * el + 1] = ((const double *)buf.data())[2 * i + 1];
+            } else {
+                dst[2 * el] = (double)((const float *)buf.data())[2 * i];
+                dst[2 * el + 1] = (double)((const float *)buf.data())[2 * i + 1];
+            }
         }
+        rebuild_row2_host(dst);
     }
     return SU3_OK;
 }

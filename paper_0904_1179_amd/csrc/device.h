@@ -392,64 +392,38 @@ __device__ __forceinline__ int chunk_order(const Geom &g, int v)
     return x0h + l0h * (x1 + g.L[1] * (x2 + g.L[2] * x3));
 }
 
-// Link storage.  The links of one (direction, parity) form a block of
-// `stride` links in tiles of kTile = 16 consecutive links; a tile holds the 9
-// complex entries as 9 rows of 16 (entry-major inside the tile):
-//   element (dir, par, n, e) at block(dir, par) + (n / 16) * 144 + e * 16 + n % 16.
+// Link storage.  A link is stored as its rows 0 and 1, the six complex
+// entries e = 3 row + col < 6; row 2 of an SU(3) matrix is conj(row 0 x row 1)
+// and is rebuilt by every reader (rebuild_row2).  The links of one
+// (direction, parity) form a block of `stride` links in tiles of kTile = 16
+// consecutive links; a tile holds the 6 entries as 6 rows of 16 (entry-major
+// inside the tile):
+//   element (dir, par, n, e) at block(dir, par) + (n / 16) * 96 + e * 16 + n % 16.
 // A wave of 64 consecutive links reads 4 tiles, 256 contiguous bytes (FP64)
-// per tile and entry: whole cache lines.  The 9 loads of one link share a
+// per tile and entry: whole cache lines.  The 6 loads of one link share a
 // single per-lane address and differ by the compile-time offset e * 16
 // elements, which the load instruction encodes as an immediate.
 constexpr int kTile = 16;
+constexpr int kEntries = 6;
 
 template <typename R>
 __device__ __forceinline__ const store_t<R> *planes(const store_t<R> *links, const Geom &g, int dir, int par)
 {
-    return links + (size_t)(dir * 2 + par) * (size_t)g.stride * 9;
+    return links + (size_t)(dir * 2 + par) * (size_t)g.stride * kEntries;
 }
 template <typename R> __device__ __forceinline__ store_t<R> *planes(store_t<R> *links, const Geom &g, int dir, int par)
 {
-    return links + (size_t)(dir * 2 + par) * (size_t)g.stride * 9;
+    return links + (size_t)(dir * 2 + par) * (size_t)g.stride * kEntries;
 }
 
 // entry 0 of link n in its block; entry e is at + e * kTile
 template <typename R> __device__ __forceinline__ const store_t<R> *link_at(const store_t<R> *block, int n)
 {
-    return block + (size_t)(n >> 4) * (9 * kTile) + (n & (kTile - 1));
+    return block + (size_t)(n >> 4) * (kEntries * kTile) + (n & (kTile - 1));
 }
 template <typename R> __device__ __forceinline__ store_t<R> *link_at(store_t<R> *block, int n)
 {
-    return block + (size_t)(n >> 4) * (9 * kTile) + (n & (kTile - 1));
-}
-
-template <typename R> __device__ __forceinline__ M3<R> load_link(const store_t<R> *block, long long, int n)
-{
-    M3<R> m;
-    const store_t<R> *p = link_at<R>(block, n);
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-        const store_t<R> v = p[e * kTile];
-        m.e[e / 3][e % 3] = Cx<R>{v.x, v.y};
-    }
-    return m;
-}
-
-// Two links loaded entry by entry in alternation.  Used for pairs of staple
-// links that are the same link for two neighbouring threads (x and x + 2 nu,
-// say): their loads then reach L2 within a few instructions of each other,
-// so the second is an L2 hit instead of a second fetch.
-template <typename R>
-__device__ __forceinline__ void load_link_pair(M3<R> &p, const store_t<R> *bp, int np, M3<R> &q, const store_t<R> *bq,
-                                               int nq, long long)
-{
-    const store_t<R> *pp = link_at<R>(bp, np), *pq = link_at<R>(bq, nq);
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-        const store_t<R> vp = pp[e * kTile];
-        const store_t<R> vq = pq[e * kTile];
-        p.e[e / 3][e % 3] = Cx<R>{vp.x, vp.y};
-        q.e[e / 3][e % 3] = Cx<R>{vq.x, vq.y};
-    }
+    return block + (size_t)(n >> 4) * (kEntries * kTile) + (n & (kTile - 1));
 }
 
 // row 2 = conj(row 0 x row 1): the third row of an SU(3) matrix, computed
@@ -510,10 +484,7 @@ template <typename R> __device__ __forceinline__ void add_to(M3<R> &C, const M3<
         }
 }
 
-// Reads of links produced by this library: only rows 0 and 1 (6 of the 9
-// entries, 2/3 of the bytes) are loaded and row 2 is rebuilt.  Every stored
-// link was reunitarised with the same row-2 formula, so the rebuilt row
-// equals the stored one up to the rounding of that formula.
+// A link as an SU(3) matrix: the stored rows 0 and 1, row 2 rebuilt.
 template <typename R> __device__ __forceinline__ M3<R> load_link12(const store_t<R> *block, int n)
 {
     M3<R> m;
@@ -568,7 +539,7 @@ template <typename R> __device__ __forceinline__ void store_link_nt(store_t<R> *
     typedef typename NtVec<R>::type V;
     V *p = reinterpret_cast<V *>(link_at<R>(block, n));
 #pragma unroll
-    for (int e = 0; e < 9; ++e) {
+    for (int e = 0; e < kEntries; ++e) {
         V v;
         v.x = m.e[e / 3][e % 3].re;
         v.y = m.e[e / 3][e % 3].im;
@@ -576,11 +547,12 @@ template <typename R> __device__ __forceinline__ void store_link_nt(store_t<R> *
     }
 }
 
-template <typename R> __device__ __forceinline__ void store_link(store_t<R> *block, long long, int n, const M3<R> &m)
+// Stores rows 0 and 1 of m (row 2 is implied).
+template <typename R> __device__ __forceinline__ void store_link(store_t<R> *block, int n, const M3<R> &m)
 {
     store_t<R> *p = link_at<R>(block, n);
 #pragma unroll
-    for (int e = 0; e < 9; ++e) {
+    for (int e = 0; e < kEntries; ++e) {
         store_t<R> v;
         v.x = m.e[e / 3][e % 3].re;
         v.y = m.e[e / 3][e % 3].im;

@@ -413,7 +413,7 @@ __global__ __launch_bounds__(kBlock) void k_polyakov(const store_t<R> *__restric
         do {
             const int lex = lex_of(g, y);
             const int par = (y[0] + y[1] + y[2] + y[3]) & 1;
-            const M3<double> u = convert<double>(load_link<R>(planes<R>(links, g, 3, par), g.stride, ly * g.Vh + (lex >> 1)));
+            const M3<double> u = convert<double>(load_link12<R>(planes<R>(links, g, 3, par), ly * g.Vh + (lex >> 1)));
             P = mul_nn(P, u);
             step<3, +1, true>(g, y, ly);
         } while (y[3] != 0 || ly != layer);
@@ -505,7 +505,7 @@ __global__ __launch_bounds__(kBlock) void k_start(store_t<R> *__restrict__ links
 #pragma unroll
             for (int c = 0; c < 3; ++c) u.e[r][c] = Cx<double>{r == c ? 1.0 : 0.0, 0.0};
     }
-    store_link<R>(planes<R>(links, g, dir, par), g.stride, n, convert<R>(u));
+    store_link<R>(planes<R>(links, g, dir, par), n, convert<R>(u));
 }
 
 template <typename R> __global__ __launch_bounds__(kBlock) void k_reunit(store_t<R> *__restrict__ links, const Geom g)
@@ -513,9 +513,9 @@ template <typename R> __global__ __launch_bounds__(kBlock) void k_reunit(store_t
     int n, dir, par, layer, x[4];
     if (!link_of_thread(g, n, dir, par, layer, x)) return;
     store_t<R> *base = planes<R>(links, g, dir, par);
-    M3<double> u = convert<double>(load_link<R>(base, g.stride, n));
+    M3<double> u = convert<double>(load_link12<R>(base, n));
     reunit(u);
-    store_link<R>(base, g.stride, n, convert<R>(u));
+    store_link<R>(base, n, convert<R>(u));
 }
 
 template <int D>
@@ -543,12 +543,12 @@ __global__ __launch_bounds__(kBlock) void k_gauge(store_t<R> *__restrict__ links
     const M3<double> gx = haar_element(gseed, site, kTagGauge);
     const M3<double> gy = haar_element(gseed, fwd, kTagGauge);
     store_t<R> *base = planes<R>(links, g, dir, par);
-    const M3<double> u = convert<double>(load_link<R>(base, g.stride, n));
+    const M3<double> u = convert<double>(load_link12<R>(base, n));
     const M3<double> t = mul_nn(gx, u);
     M3<double> out;
     set_zero(out);
     acc_nd(out, t, gy);
-    store_link<R>(base, g.stride, n, convert<R>(out));
+    store_link<R>(base, n, convert<R>(out));
 }
 
 // ---------------------------------------------------------------------------

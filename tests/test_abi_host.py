@@ -42,8 +42,9 @@ def test_footprint(hb, L, nlat, prec):
     Ls = (L,) * 4 if isinstance(L, int) else L
     V = Ls[0] * Ls[1] * Ls[2] * Ls[3]
     stride = -(-nlat * V // 2 // 64) * 64 + 64
-    assert links == 72 * stride * (16 if prec == 64 else 8)
-    assert links >= 9 * 4 * V * nlat * (16 if prec == 64 else 8)
+    # 8 (direction, parity) blocks of `stride` links, each stored as rows 0 and 1 (6 complex entries)
+    assert links == 48 * stride * (16 if prec == 64 else 8)
+    assert links >= 6 * 4 * V * nlat * (16 if prec == 64 else 8)
     assert 65536 < scratch < (1 << 20) and scratch % 256 == 0
 
 
