@@ -128,6 +128,28 @@ def fp32_deviation(L, beta, sweeps=2, seed=1):
     return out
 
 
+def config_rate(L, nlat, precision, beta, sweeps, seed=1, flip_mask=None):
+    """Link updates/s of `sweeps` sweeps (each with its plaquette) on one more
+    workload configuration, hot start excluded; also the last plaquettes."""
+    import torch
+
+    from paper_0904_1179_amd import Lattice
+
+    lat = Lattice(L, nlat=nlat, precision=precision, seed=seed, flip_mask=flip_mask)
+    lat.start(hot=True)
+    lat.sweep(1, beta)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plaq = lat.sweep_measure(sweeps, beta)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    updates = 4 * lat.V * nlat * sweeps
+    del lat
+    torch.cuda.empty_cache()
+    return {"value": updates / t, "unit": "link updates/s", "sweeps": sweeps, "seconds": t,
+            "plaquette_last": [float(x) for x in plaq[-1]]}
+
+
 def cpu_baseline(L, beta, seed=1, min_seconds=1.5, max_sweeps=64):
     """The FP64 oracle, as it stands, on the host cores: sweeps of the same
     lattice, one at a time, until min_seconds of wall time have passed."""
@@ -177,6 +199,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the mixed job stream")
+    ap.add_argument("--no-configs", action="store_true", help="skip the 2x16^4 DLT and 64^4 configurations")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -228,6 +251,14 @@ def main():
                        "achieved_gbs": round(alg32 / (r32["pass_ms"] * 1e-3) / 1e9, 1),
                        "plaquette_rel_err_vs_fp64_per_sweep": fp32_deviation(L, beta),
                        "note": "FP32 links and products; FP64 heat-bath scalars, reunitarisation and sums"}
+
+    if not args.no_configs and prec == 64:
+        # the other timed workload configurations: a double-layered 2 x 16^4 torus (flip mask 0x7) at beta 5.7,
+        # and 64^4 at beta 6.0 in both precisions (10 sweeps each after one untimed sweep)
+        out["configs"] = {
+            "dlt_2x16^4_fp64_beta5.7": config_rate(16, 2, 64, 5.7, 32, flip_mask=0x7),
+            "64^4_fp64_beta6.0": config_rate(64, 1, 64, 6.0, 10),
+            "64^4_fp32_beta6.0": config_rate(64, 1, 32, 6.0, 10)}
 
     if not args.no_serving:
         from paper_0904_1179_amd.serve import run_stream_benchmark

@@ -8,7 +8,7 @@
 namespace su3hb {
 
 // ---------------------------------------------------------------------------
-// storage types: one complex link entry per element of a component plane
+// storage types: one complex entry of a stored link
 // ---------------------------------------------------------------------------
 template <typename R> struct Store;
 template <> struct Store<double> { using type = double2; };
@@ -275,8 +275,8 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
 // ---------------------------------------------------------------------------
 // Sites are addressed by (layer, parity, i): i = lex >> 1 with
 // lex = x0 + L0 (x1 + L1 (x2 + L2 x3)); with L0 even, the two sites sharing
-// lex >> 1 have opposite parity.  Within a component plane the element of
-// site (layer, parity, i) is n = layer * Vh + i.
+// lex >> 1 have opposite parity.  Within a (direction, parity) block the
+// link of site (layer, parity, i) is element n = layer * Vh + i.
 // Unsigned division by a divisor fixed for a launch (Granlund and Montgomery,
 // "Division by invariant integers using multiplication", 1994): with
 // l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1, s1 = min(l, 1),
