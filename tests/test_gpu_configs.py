@@ -71,7 +71,8 @@ def test_fp32_first_sweeps_against_fp64_oracle(hb, L, nlat):
 @pytest.mark.parametrize("precision", [32, 64])
 def test_long_run_average_matches_oracle(hb, precision):
     """8^4, beta 5.7, cold start, 50 thermalisation + 400 measured sweeps:
-    GPU and oracle mean plaquettes agree within 4 combined standard errors."""
+    GPU and oracle mean plaquettes (independent chains) agree within 3 combined
+    standard errors of 20 binned means."""
     from oracle import su3ref
 
     _say(f"long run precision={precision}")
@@ -92,7 +93,7 @@ def test_long_run_average_matches_oracle(hb, precision):
     mg, eg = _binned(g)
     mo, eo = _binned(o)
     _say(f"  GPU {mg:.6f} +- {eg:.6f}, oracle {mo:.6f} +- {eo:.6f}")
-    assert abs(mg - mo) < 4 * np.hypot(eg, eo)
+    assert abs(mg - mo) < 3 * np.hypot(eg, eo)
     _, att, acc = lat.counters()
     assert 0.96 < acc / att < 0.98  # the paper's 97.2 % 1-hit acceptance at beta = 5.7
 
