@@ -205,20 +205,55 @@ __host__ __device__ inline double cospi_sq_0to2(double t)
     return ((int)q & 1) ? s * s : c * c;
 }
 
-// Precision-generic helpers of the heat bath.  FP64: the functions above
-// (arguments: uniforms in (0, 1] and t in [0, 2]); FP32: the library ones.
+// FP32 versions for the FP32 tier: the same reduction, Taylor series cut where
+// the first omitted term is below 3e-9 at |pi r| = pi/4 (sine j = 0..4,
+// cosine j = 0..5), coefficients as above rounded to float.
+__host__ __device__ inline void sincospi_quarter(float r, float *sn, float *cs)
+{
+    const float y = r * r;
+    float ps = 0.08214588661112823f;
+    ps = fmaf(ps, y, -0.5992645293207921f);
+    ps = fmaf(ps, y, 2.5501640398773455f);
+    ps = fmaf(ps, y, -5.16771278004997f);
+    ps = fmaf(ps, y, 3.141592653589793f);
+    float pc = -0.02580689139001406f;
+    pc = fmaf(pc, y, 0.2353306303588932f);
+    pc = fmaf(pc, y, -1.3352627688545895f);
+    pc = fmaf(pc, y, 4.0587121264167685f);
+    pc = fmaf(pc, y, -4.934802200544679f);
+    *sn = r * ps;
+    *cs = fmaf(pc, y, 1.0f);
+}
+__host__ __device__ inline void sincospi_0to2(float t, float *sn, float *cs)
+{
+    const float q = rintf(t + t);
+    const float r = fmaf(q, -0.5f, t);
+    float s, c;
+    sincospi_quarter(r, &s, &c);
+    const int iq = (int)q & 3;
+    const float ss = (iq & 1) ? c : s, cc = (iq & 1) ? s : c;
+    *sn = (iq & 2) ? -ss : ss;
+    *cs = (iq == 1 || iq == 2) ? -cc : cc;
+}
+__host__ __device__ inline float cospi_sq_0to2(float t)
+{
+    const float q = rintf(t + t);
+    const float r = fmaf(q, -0.5f, t);
+    float s, c;
+    sincospi_quarter(r, &s, &c);
+    return ((int)q & 1) ? s * s : c * c;
+}
+
+// Precision-generic helpers of the heat bath (arguments: uniforms in (0, 1]
+// and t in [0, 2]): the functions above; FP32 logarithm from the library.
 __device__ __forceinline__ double log_r(double x) { return log_unit(x); }
 __device__ __forceinline__ float log_r(float x) { return logf(x); }
 __device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
 __device__ __forceinline__ float sqrt_r(float x) { return sqrtf(x); }
 __device__ __forceinline__ double cospi_sq_r(double t) { return cospi_sq_0to2(t); }
-__device__ __forceinline__ float cospi_sq_r(float t)
-{
-    const float c = cospif(t);
-    return c * c;
-}
+__device__ __forceinline__ float cospi_sq_r(float t) { return cospi_sq_0to2(t); }
 __device__ __forceinline__ void sincospi_r(double t, double *s, double *c) { sincospi_0to2(t, s, c); }
-__device__ __forceinline__ void sincospi_r(float t, float *s, float *c) { sincospif(t, s, c); }
+__device__ __forceinline__ void sincospi_r(float t, float *s, float *c) { sincospi_0to2(t, s, c); }
 
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11)
