@@ -243,6 +243,7 @@ __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, co
     site_coords(g, par, i, x);
     M3<R> A, S;
     set_zero(A);
+    __builtin_amdgcn_s_setprio(1);  // gathering the staple: issue loads ahead of waves in the heat bath
     if constexpr (!kStashOrder<R, DLT>) {
         // b and e of each direction loaded in its phase
         const store_t<R> *umu = planes<R>(links, g, MU, par ^ 1);
@@ -293,6 +294,7 @@ __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, co
     M3<R> U = load_link12_nt<R>(own, n);
     const uint64_t site = (uint64_t)layer * (uint64_t)(2 * g.Vh) + (uint64_t)lex_of(g, x);
     // with per-layer couplings the staple carries them: alpha = 2k/3
+    __builtin_amdgcn_s_setprio(0);
     double trw = heatbath<R, HIT1>(U, A, TWOB ? 1.0 : beta, seed, 4 * site + MU, sweep, nhit, att, acc);
     store_link_nt<R>(own, n, U);
     if constexpr (MEAS && MU < 3) trw = retr_mul(U, S);
