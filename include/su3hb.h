@@ -194,7 +194,8 @@ su3_status su3_stream_copy(void *dst, const void *src, size_t bytes, void *hip_s
  * what fits, runs one sweep of every admitted job -- 8 batched launches, one
  * per checkerboard pass, each covering all jobs of a precision -- and retires
  * the jobs that reached their sweep count (final plaquette and heat-bath
- * counters kept, memory freed).  A job's links get the same per-link
+ * counters kept, memory freed); su3_server_run does the same for several
+ * sweeps per call.  A job's links get the same per-link
  * arithmetic and the same keyed random numbers as a single lattice run with
  * su3_start/su3_sweep, so its result is the same alone and in the mix.
  * su3_server_step synchronises the server's stream.
@@ -228,6 +229,13 @@ su3_status su3_server_create(void *d_arena, size_t arena_bytes, int32_t max_acti
 su3_status su3_server_submit(su3_server *s, const su3_job *job, int64_t *job_id);
 /* Admit, run one batched sweep, retire; counts after the step (any pointer may be NULL). */
 su3_status su3_server_step(su3_server *s, int32_t *n_active, int32_t *n_queued, int32_t *n_finished);
+/* As su3_server_step, but runs k = min(max_sweeps, fewest remaining sweeps of
+ * an admitted job) sweeps before retiring, with a single synchronisation: no
+ * job finishes inside the call, and every job's results are those of k single
+ * steps.  Newly submitted jobs wait for the call to end before admission.
+ * SU3_EINVAL if max_sweeps < 1. */
+su3_status su3_server_run(su3_server *s, int32_t max_sweeps, int32_t *n_active, int32_t *n_queued,
+                          int32_t *n_finished);
 su3_status su3_server_poll(su3_server *s, int64_t job_id, su3_job_result *out);
 su3_status su3_server_stats(su3_server *s, size_t *arena_used, size_t *arena_peak, uint64_t *steps);
 /* Waits for the stream, frees host resources; never frees the arena. */

@@ -446,18 +446,22 @@ __global__ __launch_bounds__(kBlock) void k_polyakov_final(const double *__restr
 }
 
 // Batched pass: one launch updates the links U_MU of parity `par` of every
-// job in `jobs` (sorted by tile_begin).  Workgroup b belongs to the job whose
-// tile range holds b; job j is at sweep index sweep0 + (step - admit_step).
+// job in `jobs` (sorted by tile_begin).  The grid has one workgroup per tile
+// of the batch; logical tile t (pass_tile) belongs to the job whose tile range
+// holds t; job j is at sweep index sweep0 + (step - admit_step).
 template <int MU, typename R, bool HIT1>
 __global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update_batch(const BatchJob *__restrict__ jobs, const int njobs,
                                                          const long long step, const int par)
 {
+    // the XCD-aware, parity-reversed tile of the whole batch, as for one
+    // lattice: each XCD works on contiguous stretches of each job's tiles
+    const int t = pass_tile(par);
     __shared__ int sj;
     if (threadIdx.x == 0) {
         int lo = 0, hi = njobs - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (jobs[mid].tile_begin <= (int)blockIdx.x)
+            if (jobs[mid].tile_begin <= t)
                 lo = mid;
             else
                 hi = mid - 1;
@@ -466,7 +470,7 @@ __global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update_batch(const Ba
     }
     __syncthreads();
     const BatchJob &J = jobs[sj];
-    const int local = (int)blockIdx.x - J.tile_begin;
+    const int local = t - J.tile_begin;
     const int v = local * kBlock + threadIdx.x;
     const uint64_t sweep = J.sweep0 + (uint64_t)(step - J.admit_step);
     int att = 0, acc = 0;

@@ -220,9 +220,17 @@ su3_status su3_server_submit(su3_server *s, const su3_job *job, int64_t *job_id)
     return SU3_OK;
 }
 
-su3_status su3_server_step(su3_server *s, int32_t *n_active, int32_t *n_queued, int32_t *n_finished)
+}  // extern "C"
+
+namespace {
+
+// Admit, run k sweeps of every admitted job (k = min(max_sweeps, fewest
+// remaining sweeps of an active job), so no job finishes inside the call),
+// then retire with one synchronisation.
+su3_status run_sweeps(su3_server *s, int32_t max_sweeps, int32_t *n_active, int32_t *n_queued, int32_t *n_finished)
 {
     if (!s) return fail(SU3_EINVAL, "server is NULL");
+    if (max_sweeps < 1) return fail(SU3_EINVAL, "max_sweeps must be >= 1");
     hipError_t e;
     // admission: first come, first served, while a slot and the footprint are free
     while (!s->queue.empty() && (int)s->active.size() < s->max_active) {
@@ -247,20 +255,28 @@ su3_status su3_server_step(su3_server *s, int32_t *n_active, int32_t *n_queued, 
             su3_status st = build_tables(s);
             if (st != SU3_OK) return st;
         }
-        for (int mu = 0; mu < 4; ++mu)
-            for (int par = 0; par < 2; ++par)
-                for (int gi = 0; gi < kGroups; ++gi) {
-                    const Group &G = s->groups[gi];
-                    if (!G.njobs) continue;
-                    e = launch_update_batch(gi < 2 ? 64 : 32, (gi & 1) == 0, G.d_table, G.njobs, G.ntiles, s->step, mu,
-                                            par, s->stream);
-                    if (e != hipSuccess) return hip_fail(e, "batched pass");
-                }
-        s->step += 1;
+        int k = max_sweeps;
+        for (int64_t id : s->active) {
+            const Job &j = s->jobs[id];
+            k = std::min(k, j.spec.nsweeps - j.sweeps_done);
+        }
+        for (int sw = 0; sw < k; ++sw) {
+            for (int mu = 0; mu < 4; ++mu)
+                for (int par = 0; par < 2; ++par)
+                    for (int gi = 0; gi < kGroups; ++gi) {
+                        const Group &G = s->groups[gi];
+                        if (!G.njobs) continue;
+                        e = launch_update_batch(gi < 2 ? 64 : 32, (gi & 1) == 0, G.d_table, G.njobs, G.ntiles, s->step,
+                                                mu, par, s->stream);
+                        if (e != hipSuccess) return hip_fail(e, "batched pass");
+                    }
+            s->step += 1;
+        }
         std::vector<int64_t> done;
         for (int64_t id : s->active) {
             Job &j = s->jobs[id];
-            if (++j.sweeps_done == j.spec.nsweeps) {
+            j.sweeps_done += k;
+            if (j.sweeps_done == j.spec.nsweeps) {
                 j.slot = (int)done.size();
                 done.push_back(id);
             }
@@ -302,6 +318,21 @@ su3_status su3_server_step(su3_server *s, int32_t *n_active, int32_t *n_queued, 
     if (n_queued) *n_queued = (int32_t)s->queue.size();
     if (n_finished) *n_finished = finished;
     return SU3_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+su3_status su3_server_step(su3_server *s, int32_t *n_active, int32_t *n_queued, int32_t *n_finished)
+{
+    return run_sweeps(s, 1, n_active, n_queued, n_finished);
+}
+
+su3_status su3_server_run(su3_server *s, int32_t max_sweeps, int32_t *n_active, int32_t *n_queued,
+                          int32_t *n_finished)
+{
+    return run_sweeps(s, max_sweeps, n_active, n_queued, n_finished);
 }
 
 su3_status su3_server_poll(su3_server *s, int64_t job_id, su3_job_result *out)

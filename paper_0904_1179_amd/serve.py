@@ -31,6 +31,7 @@ for _name, _res, _args in (
         ("su3_server_create", _st, [_vp, C.c_size_t, C.c_int32, _vp, C.POINTER(_vp)]),
         ("su3_server_submit", _st, [_vp, C.POINTER(su3_job), C.POINTER(C.c_int64)]),
         ("su3_server_step", _st, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        ("su3_server_run", _st, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         ("su3_server_poll", _st, [_vp, C.c_int64, C.POINTER(su3_job_result)]),
         ("su3_server_stats", _st, [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(C.c_uint64)]),
         ("su3_server_destroy", _st, [_vp])):
@@ -76,6 +77,13 @@ class Server:
         _hb._check(_lib.su3_server_step(self.h, C.byref(a), C.byref(q), C.byref(f)), "su3_server_step")
         return a.value, q.value, f.value
 
+    def run(self, max_sweeps):
+        """su3_server_run: up to max_sweeps sweeps of every admitted job, one synchronisation."""
+        a, q, f = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        _hb._check(_lib.su3_server_run(self.h, int(max_sweeps), C.byref(a), C.byref(q), C.byref(f)),
+                   "su3_server_run")
+        return a.value, q.value, f.value
+
     def poll(self, jid):
         r = su3_job_result()
         _hb._check(_lib.su3_server_poll(self.h, int(jid), C.byref(r)), "su3_server_poll")
@@ -92,13 +100,15 @@ def _volume(L):
     return int(np.prod(L)) if isinstance(L, (tuple, list)) else int(L) ** 4
 
 
-def run_stream(jobs, arena_bytes=4 << 30, max_active=256, realtime=True):
+def run_stream(jobs, arena_bytes=4 << 30, max_active=256, realtime=True, sweeps_per_call=8):
     """Feed `jobs` (dicts from workloads.serving_stream) into a server.
 
     realtime: a job is submitted once the wall clock passes its arrival time;
-    otherwise everything is submitted at once.  Returns (records, summary):
-    per job its arrival, completion and latency (seconds since the stream
-    started) and final plaquette/counters."""
+    otherwise everything is submitted at once.  Each server call runs up to
+    `sweeps_per_call` sweeps (su3_server_run), so the per-call launch and
+    synchronisation cost is shared by several sweeps.  Returns (records,
+    summary): per job its arrival, completion and latency (seconds since the
+    stream started) and final plaquette/counters."""
     srv = Server(arena_bytes, max_active)
     order = sorted(jobs, key=lambda j: j["arrival"])
     ids, recs = {}, {}
@@ -113,7 +123,7 @@ def run_stream(jobs, arena_bytes=4 << 30, max_active=256, realtime=True):
             ids[jid] = j
             recs[j["id"]] = {"arrival": j["arrival"] if realtime else 0.0, "submitted": now}
             nxt += 1
-        active, queued, finished = srv.step()
+        active, queued, finished = srv.run(sweeps_per_call)
         if finished:
             t = time.perf_counter() - t0
             for jid, j in ids.items():
@@ -136,7 +146,8 @@ def run_stream(jobs, arena_bytes=4 << 30, max_active=256, realtime=True):
                "p99_latency_s": float(np.percentile(lat, 99)), "mean_latency_s": float(lat.mean()),
                "max_latency_s": float(lat.max()), "link_updates": int(updates),
                "throughput_updates_per_s": updates / wall, "arena_bytes": int(arena_bytes),
-               "arena_peak_bytes": st["arena_peak"], "max_active": max_active, "steps": st["steps"]}
+               "arena_peak_bytes": st["arena_peak"], "max_active": max_active, "steps": st["steps"],
+               "sweeps_per_call": sweeps_per_call}
     return recs, summary
 
 

@@ -30,6 +30,11 @@ class su3_params(C.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (hipcc, gfx950) first")
+    # PyTorch ships its own HIP runtime under the same soname as ROCm's
+    # (libamdhip64.so.7).  Loaded first, it is the one this library binds to,
+    # so device memory and streams that torch hands over belong to the same
+    # runtime; loaded the other way round, the process would hold two.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     st, vp, u64, sz, dp = C.c_int, C.c_void_p, C.c_uint64, C.c_size_t, C.POINTER(C.c_double)
     P = C.POINTER(su3_params)

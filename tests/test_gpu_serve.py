@@ -49,7 +49,8 @@ def _alone(hb, L, nlat, prec, beta, nsw, seed, hot, nhit):
     return lat.plaquette(), lat.counters()[1:]
 
 
-def test_each_result_identical_alone_and_in_the_mix(hb):
+@pytest.mark.parametrize("sweeps_per_call", [1, 8])
+def test_each_result_identical_alone_and_in_the_mix(hb, sweeps_per_call):
     from paper_0904_1179_amd import serve
 
     jobs = [{"id": k, "arrival": 0.0, "L": L, "nlat": nlat, "precision": prec, "beta": beta, "nsweeps": nsw,
@@ -59,7 +60,8 @@ def test_each_result_identical_alone_and_in_the_mix(hb):
     p12 = hb.make_params(12, precision=32)
     nl, ns = hb.su3_footprint(p12)
     arena = 3 * (nl + ns) + (1 << 20)
-    recs, summary = serve.run_stream(jobs, arena_bytes=arena, max_active=4, realtime=False)
+    recs, summary = serve.run_stream(jobs, arena_bytes=arena, max_active=4, realtime=False,
+                                     sweeps_per_call=sweeps_per_call)
     _say(f"mix: {summary['steps']} steps, arena peak {summary['arena_peak_bytes']} of {arena}")
     assert summary["arena_peak_bytes"] <= arena
     for k, spec in enumerate(MIX):
@@ -110,6 +112,9 @@ def test_invalid_jobs_rejected(hb):
         with pytest.raises(hb.SU3Error) as e:
             srv.submit(bad)
         assert e.value.status == -1
+    with pytest.raises(hb.SU3Error) as e:
+        srv.run(0)
+    assert e.value.status == -1
 
 
 def test_short_realtime_stream(hb):
