@@ -97,6 +97,8 @@ SWEEP_CASES = [
     ((4, 4, 6, 4), 1, None, True, 0.5, 1, 2),      # strong coupling, low acceptance
     ((4, 4, 4, 4), 1, None, True, 50.0, 1, 2),     # weak coupling
     ((4, 6, 4, 4), 1, None, True, 5.7, 3, 2),      # 3 attempts per subgroup
+    ((4, 6, 24, 6), 1, None, True, 5.7, 1, 2),     # chunk width 3: divisors 2, 6, 3, 6 of the pass order
+    ((6, 10, 24, 2), 2, 0x7, True, 5.7, 1, 2),     # DLT with chunk width 3 and extents 3, 10, 24, 2
 ]
 
 
