@@ -20,8 +20,6 @@ namespace su3hb {
 
 namespace {
 
-constexpr double kTwoPi = 6.283185307179586476925286766559;
-
 // ---------------------------------------------------------------------------
 // staple: A += U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+ + U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)
 // written as a (c b)^+ + (e d)^+ f with
@@ -163,8 +161,10 @@ template <typename R> __device__ __forceinline__ double retr_mul(const M3<R> &u,
 }
 
 // One thread of a pass: the link U_MU at pass-order position v of its layer
-// (v < nlat * Vh).  Shared by the single-lattice and the batched kernels, so
-// a lattice gets bit-identical updates from both.
+// (v < nlat * Vh).  Shared by the single-lattice and the batched kernels: the
+// two may load the staple links in different orders (below), but every value
+// goes through the same arithmetic in the same order, so a lattice gets
+// bit-identical updates from both.
 //
 // Load order (single torus).  The six links U_MU(x +- nu) (b and e of the
 // three staple directions) are links of the other parity that the
