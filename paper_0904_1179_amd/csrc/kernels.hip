@@ -91,9 +91,9 @@ __device__ __forceinline__ double heatbath(M3<R> &U, const M3<R> &A, double beta
         const R v1 = R(-0.5) * (W.e[i][j].im + W.e[j][i].im);
         const R v2 = R(0.5) * (W.e[j][i].re - W.e[i][j].re);
         const R v3 = R(0.5) * (W.e[j][j].im - W.e[i][i].im);
-        const R k = sqrt_r(v0 * v0 + v1 * v1 + v2 * v2 + v3 * v3);
-        if (k == R(0)) continue;
-        const R rk = R(1) / k;
+        const R k2 = v0 * v0 + v1 * v1 + v2 * v2 + v3 * v3;
+        if (k2 == R(0)) continue;
+        const R rk = rsqrt_r(k2);  // 1/k
         const R inv2alpha = q34b * rk;
         bool ok = false;
         R a0 = R(1), a1 = R(0), a2 = R(0), a3 = R(0);
@@ -111,11 +111,12 @@ __device__ __forceinline__ double heatbath(M3<R> &U, const M3<R> &A, double beta
                 const R u6 = R(unif32((uint32_t)(w.w[3] >> 32)));
                 a0 = R(1) - R(2) * lam2;
                 const R cth = R(2) * u5 - R(1);
-                const R sth = sqrt_r(R(1) - cth * cth);
+                // FP64: |cth| < 1 (u5 is never 0 or 1), so the argument is positive
+                const R sth = sqrt_pos_r(R(1) - cth * cth);
                 R sph, cph;
                 sincospi_r(R(2) * u6, &sph, &cph);
                 const R rho2 = R(1) - a0 * a0;
-                const R rho = rho2 > R(0) ? sqrt_r(rho2) : R(0);
+                const R rho = rho2 > R(0) ? sqrt_pos_r(rho2) : R(0);
                 a1 = rho * sth * cph;
                 a2 = rho * sth * sph;
                 a3 = rho * cth;
