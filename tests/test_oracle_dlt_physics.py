@@ -104,3 +104,27 @@ def test_strong_coupling_per_layer():
         mean, err = batch_mean_error(series[:, layer], nbins=20)
         u = weyl_u(beta)
         assert abs(mean - u) < 4 * err + 4 * u ** 5, (layer, mean, u, err)
+
+
+def test_dlt_layers_equilibrate_like_the_single_torus():
+    """beta 5.7, flip mask 0x7: the mean plaquettes of the two layers of a
+    2 x 8^4 double-layered torus agree with each other and with an 8^4 single
+    torus within 3 combined standard errors (binned), whatever the gluing:
+    locally every site sees the same action."""
+    dlt = su3ref.Oracle(8, nlat=2, seed=41)
+    pbc = su3ref.Oracle(8, nlat=1, seed=42)
+    series = {"dlt": [], "pbc": []}
+    for name, lat in (("dlt", dlt), ("pbc", pbc)):
+        lat.start(False)
+        lat.sweep(60, 5.7)
+        for _ in range(300):
+            lat.sweep(1, 5.7)
+            series[name].append(lat.plaquette())
+    d = np.array(series["dlt"])
+    p = np.array(series["pbc"])
+    m0, e0 = batch_mean_error(d[:, 1], nbins=20)
+    m1, e1 = batch_mean_error(d[:, 2], nbins=20)
+    mp, ep = batch_mean_error(p[:, 0], nbins=20)
+    assert abs(m0 - m1) < 3 * np.hypot(e0, e1), (m0, e0, m1, e1)
+    assert abs(m0 - mp) < 3 * np.hypot(e0, ep), (m0, e0, mp, ep)
+    assert abs(m1 - mp) < 3 * np.hypot(e1, ep), (m1, e1, mp, ep)
