@@ -191,8 +191,9 @@ su3_status su3_stream_copy(void *dst, const void *src, size_t bytes, void *hip_s
  * jobs wait in submission order and are admitted when fewer than max_active
  * jobs run and a first-fit allocation of the job's footprint (su3_footprint:
  * links + scratch) succeeds inside the buffer.  Each su3_server_step admits
- * what fits, runs one sweep of every admitted job -- 8 batched launches, one
- * per checkerboard pass, each covering all jobs of a precision -- and retires
+ * what fits, runs one sweep of every admitted job -- 8 batched launches per
+ * group of jobs with the same precision, hit count and geometry, one per
+ * checkerboard pass -- and retires
  * the jobs that reached their sweep count (final plaquette and heat-bath
  * counters kept, memory freed); su3_server_run does the same for several
  * sweeps per call.  A job's links get the same per-link

@@ -450,10 +450,15 @@ __global__ __launch_bounds__(kBlock) void k_polyakov_final(const double *__restr
 // job in `jobs` (sorted by tile_begin).  The grid has one workgroup per tile
 // of the batch; logical tile t (pass_tile) belongs to the job whose tile range
 // holds t; job j is at sweep index sweep0 + (step - admit_step).
-template <int MU, typename R, bool HIT1>
+template <int MU, typename R, bool HIT1, bool DLT>
 __global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update_batch(const BatchJob *__restrict__ jobs, const int njobs,
                                                          const long long step, const int par)
 {
+    store_t<R> *st = nullptr;
+    if constexpr (kStashOrder<R, DLT>) {
+        __shared__ store_t<R> stash[kStashSlots * 6 * kBlock];
+        st = stash;
+    }
     // the XCD-aware, parity-reversed tile of the whole batch, as for one
     // lattice: each XCD works on contiguous stretches of each job's tiles
     const int t = pass_tile(par);
@@ -476,8 +481,8 @@ __global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update_batch(const Ba
     const uint64_t sweep = J.sweep0 + (uint64_t)(step - J.admit_step);
     int att = 0, acc = 0;
     if (v < J.g.nlat * J.g.Vh)
-        update_link<MU, R, HIT1, true>((store_t<R> *)J.links, J.g, par, v, J.beta, sweep, J.seed, J.nhit, att, acc,
-                                       nullptr);
+        update_link<MU, R, HIT1, DLT>((store_t<R> *)J.links, J.g, par, v, J.beta, sweep, J.seed, J.nhit, att, acc,
+                                      st);
     count_block(att, acc, J.counters, local % kCounterSlots);
 }
 
@@ -749,32 +754,39 @@ hipError_t launch_update(int precision, void *links, const Geom &g, int mu, int 
     return hipGetLastError();
 }
 
-template <typename R, bool HIT1>
+template <typename R, bool HIT1, bool DLT>
 static void batch_dispatch(const BatchJob *jobs, int njobs, int ntiles, long long step, int mu, int par, hipStream_t s)
 {
     switch (mu) {
-    case 0: k_update_batch<0, R, HIT1><<<ntiles, kBlock, 0, s>>>(jobs, njobs, step, par); break;
-    case 1: k_update_batch<1, R, HIT1><<<ntiles, kBlock, 0, s>>>(jobs, njobs, step, par); break;
-    case 2: k_update_batch<2, R, HIT1><<<ntiles, kBlock, 0, s>>>(jobs, njobs, step, par); break;
-    default: k_update_batch<3, R, HIT1><<<ntiles, kBlock, 0, s>>>(jobs, njobs, step, par); break;
+    case 0: k_update_batch<0, R, HIT1, DLT><<<ntiles, kBlock, 0, s>>>(jobs, njobs, step, par); break;
+    case 1: k_update_batch<1, R, HIT1, DLT><<<ntiles, kBlock, 0, s>>>(jobs, njobs, step, par); break;
+    case 2: k_update_batch<2, R, HIT1, DLT><<<ntiles, kBlock, 0, s>>>(jobs, njobs, step, par); break;
+    default: k_update_batch<3, R, HIT1, DLT><<<ntiles, kBlock, 0, s>>>(jobs, njobs, step, par); break;
     }
 }
 
-hipError_t launch_update_batch(int precision, bool hit1, const BatchJob *d_jobs, int njobs, int ntiles, long long step,
-                               int mu, int par, hipStream_t s)
+template <typename R>
+static void batch_dispatch_r(bool hit1, bool dlt, const BatchJob *jobs, int njobs, int ntiles, long long step, int mu,
+                             int par, hipStream_t s)
+{
+    if (hit1 && !dlt)
+        batch_dispatch<R, true, false>(jobs, njobs, ntiles, step, mu, par, s);
+    else if (hit1)
+        batch_dispatch<R, true, true>(jobs, njobs, ntiles, step, mu, par, s);
+    else if (!dlt)
+        batch_dispatch<R, false, false>(jobs, njobs, ntiles, step, mu, par, s);
+    else
+        batch_dispatch<R, false, true>(jobs, njobs, ntiles, step, mu, par, s);
+}
+
+hipError_t launch_update_batch(int precision, bool hit1, bool dlt, const BatchJob *d_jobs, int njobs, int ntiles,
+                               long long step, int mu, int par, hipStream_t s)
 {
     if (njobs <= 0 || ntiles <= 0) return hipSuccess;
-    if (precision == 64) {
-        if (hit1)
-            batch_dispatch<double, true>(d_jobs, njobs, ntiles, step, mu, par, s);
-        else
-            batch_dispatch<double, false>(d_jobs, njobs, ntiles, step, mu, par, s);
-    } else {
-        if (hit1)
-            batch_dispatch<float, true>(d_jobs, njobs, ntiles, step, mu, par, s);
-        else
-            batch_dispatch<float, false>(d_jobs, njobs, ntiles, step, mu, par, s);
-    }
+    if (precision == 64)
+        batch_dispatch_r<double>(hit1, dlt, d_jobs, njobs, ntiles, step, mu, par, s);
+    else
+        batch_dispatch_r<float>(hit1, dlt, d_jobs, njobs, ntiles, step, mu, par, s);
     return hipGetLastError();
 }
 

@@ -31,9 +31,10 @@ hipError_t launch_start(int precision, void *links, const Geom &g, int hot, uint
 hipError_t launch_update(int precision, void *links, const Geom &g, int mu, int par, double beta, uint64_t sweep,
                          uint64_t seed, int nhit, unsigned long long *counters, hipStream_t s);
 // one pass (mu, par) of every job in d_jobs (device copy, sorted by tile_begin);
-// all jobs share `precision`; hit1: every job has nhit = 1
-hipError_t launch_update_batch(int precision, bool hit1, const BatchJob *d_jobs, int njobs, int ntiles, long long step,
-                               int mu, int par, hipStream_t s);
+// all jobs share `precision`; hit1: every job has nhit = 1; dlt: every job is
+// a double-layered torus (else every job is a single torus)
+hipError_t launch_update_batch(int precision, bool hit1, bool dlt, const BatchJob *d_jobs, int njobs, int ntiles,
+                               long long step, int mu, int par, hipStream_t s);
 hipError_t launch_plaquette(int precision, const void *links, const Geom &g, double *partials, double *sums,
                             hipStream_t s);
 // Single torus: the odd pass of mu (1, 2 or 3) that also stores, per

@@ -26,7 +26,7 @@ using namespace su3hb;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kGroups = 4;  // (precision 64/32) x (1-hit / general)
+constexpr int kGroups = 8;  // (precision 64/32) x (1-hit / general) x (single / double-layered torus)
 
 size_t align_up(size_t a) { return (a + kAlign - 1) / kAlign * kAlign; }
 
@@ -105,7 +105,10 @@ struct su3_server {
 
 namespace {
 
-int group_of(const su3_job &j) { return (j.params.precision == 64 ? 0 : 2) + (j.params.nhit == 1 ? 0 : 1); }
+int group_of(const su3_job &j)
+{
+    return (j.params.precision == 64 ? 0 : 4) + (j.params.nhit == 1 ? 0 : 2) + (j.params.nlat == 2 ? 1 : 0);
+}
 
 su3_status check_job(const su3_job *j)
 {
@@ -266,8 +269,8 @@ su3_status run_sweeps(su3_server *s, int32_t max_sweeps, int32_t *n_active, int3
                     for (int gi = 0; gi < kGroups; ++gi) {
                         const Group &G = s->groups[gi];
                         if (!G.njobs) continue;
-                        e = launch_update_batch(gi < 2 ? 64 : 32, (gi & 1) == 0, G.d_table, G.njobs, G.ntiles, s->step,
-                                                mu, par, s->stream);
+                        e = launch_update_batch(gi < 4 ? 64 : 32, (gi & 2) == 0, (gi & 1) != 0, G.d_table, G.njobs,
+                                                G.ntiles, s->step, mu, par, s->stream);
                         if (e != hipSuccess) return hip_fail(e, "batched pass");
                     }
             s->step += 1;
