@@ -175,10 +175,8 @@ template <typename R> __device__ __forceinline__ double retr_mul(const M3<R> &u,
 // phase, b and e of the second and b of the third wait in this thread's slots
 // of `stash` (3 * 6 * kBlock entries of LDS, slot-major, so the 64 lanes of a
 // wave access consecutive entries), e of the third stays in registers.  This
-// order is used where kStashOrder holds; otherwise (FP32, whose pass is
-// bound by instruction issue, and the double-layered torus, where six
-// layer-dependent addresses at once would spill) b and e are loaded in their
-// direction's phase and `stash` is unused.
+// order is used with STASH (kStashPass, kStashBatch); otherwise b and e are
+// loaded in their direction's phase and `stash` is unused.
 //
 // MEAS: also return Re Tr(U_new S) with S the staple terms of the directions
 // nu < MU.  Summed over the sites of one parity these are all plaquettes of
@@ -193,11 +191,13 @@ constexpr int kStashSlots = 3;
 // FP64, 36 KiB in FP32 per workgroup) fits the 160 KiB of LDS at these
 // occupancies.
 template <typename R> constexpr int kPassWaves = sizeof(R) == 8 ? 2 : 4;
-// The stash order pays where a pass is limited by memory traffic: FP64 on a
-// single torus.  The FP32 pass is limited by instruction issue (FP32 and
-// FP64 vector operations issue at the same rate), so it keeps the
-// direction-by-direction order, as does the double-layered torus.
-template <typename R, bool DLT> constexpr bool kStashOrder = !DLT && sizeof(R) == 8;
+// The stash order pays where a pass is limited by memory traffic: FP64.  The
+// FP32 pass is limited by instruction issue (FP32 and FP64 vector operations
+// issue at the same rate), so it keeps the direction-by-direction order.  On
+// a double-layered torus the six layer-dependent addresses of MU = 0 at once
+// spill, and so does the batched pass (which also holds its job record).
+template <typename R, bool DLT, int MU> constexpr bool kStashPass = sizeof(R) == 8 && (!DLT || MU > 0);
+template <typename R, bool DLT> constexpr bool kStashBatch = sizeof(R) == 8 && !DLT;
 template <typename R> struct Raw12 {
     store_t<R> v[6];  // rows 0 and 1 as stored
 };
@@ -227,7 +227,7 @@ template <typename R> __device__ __forceinline__ M3<R> stash_get(const store_t<R
 }
 __device__ __forceinline__ void stash_fence() { __asm__ __volatile__("" ::: "memory"); }
 
-template <int MU, typename R, bool HIT1, bool DLT, bool TWOB = false, bool MEAS = false>
+template <int MU, typename R, bool HIT1, bool DLT, bool TWOB = false, bool MEAS = false, bool STASH = false>
 __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, const Geom &g, int par, int v,
                                               double beta, uint64_t sweep, uint64_t seed, int nhit, int &att, int &acc,
                                               store_t<R> *stash, const R *wb = nullptr)
@@ -245,7 +245,7 @@ __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, co
     M3<R> A, S;
     set_zero(A);
     __builtin_amdgcn_s_setprio(1);  // gathering the staple: issue loads ahead of waves in the heat bath
-    if constexpr (!kStashOrder<R, DLT>) {
+    if constexpr (!STASH) {
         // b and e of each direction loaded in its phase
         const store_t<R> *umu = planes<R>(links, g, MU, par ^ 1);
         M3<R> b, e;
@@ -264,12 +264,12 @@ __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, co
         Raw12<R> b0, e0, b1, e1, b2, e2;
         {
             const store_t<R> *umu = planes<R>(links, g, MU, par ^ 1);
-            const store_t<R> *pb0 = link_at<R>(umu, nbr_elem<N0, +1, MU, 0, false>(g, x, layer));
-            const store_t<R> *pe0 = link_at<R>(umu, nbr_elem<N0, -1, MU, 0, false>(g, x, layer));
-            const store_t<R> *pb1 = link_at<R>(umu, nbr_elem<N1, +1, MU, 0, false>(g, x, layer));
-            const store_t<R> *pe1 = link_at<R>(umu, nbr_elem<N1, -1, MU, 0, false>(g, x, layer));
-            const store_t<R> *pb2 = link_at<R>(umu, nbr_elem<N2, +1, MU, 0, false>(g, x, layer));
-            const store_t<R> *pe2 = link_at<R>(umu, nbr_elem<N2, -1, MU, 0, false>(g, x, layer));
+            const store_t<R> *pb0 = link_at<R>(umu, nbr_elem<N0, +1, MU, 0, DLT>(g, x, layer));
+            const store_t<R> *pe0 = link_at<R>(umu, nbr_elem<N0, -1, MU, 0, DLT>(g, x, layer));
+            const store_t<R> *pb1 = link_at<R>(umu, nbr_elem<N1, +1, MU, 0, DLT>(g, x, layer));
+            const store_t<R> *pe1 = link_at<R>(umu, nbr_elem<N1, -1, MU, 0, DLT>(g, x, layer));
+            const store_t<R> *pb2 = link_at<R>(umu, nbr_elem<N2, +1, MU, 0, DLT>(g, x, layer));
+            const store_t<R> *pe2 = link_at<R>(umu, nbr_elem<N2, -1, MU, 0, DLT>(g, x, layer));
 #pragma unroll
             for (int e = 0; e < 6; ++e) {
                 b0.v[e] = pb0[e * kTile];
@@ -362,8 +362,9 @@ __global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update(store_t<R> *__
                                                    const int nhit, unsigned long long *__restrict__ counters,
                                                    double *__restrict__ meas = nullptr)
 {
+    constexpr bool kStash = kStashPass<R, DLT, MU>;
     store_t<R> *st = nullptr;
-    if constexpr (kStashOrder<R, DLT>) {
+    if constexpr (kStash) {
         __shared__ store_t<R> stash[kStashSlots * 6 * kBlock];
         st = stash;
     }
@@ -371,7 +372,8 @@ __global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update(store_t<R> *__
     int att = 0, acc = 0;
     double trw = 0.0;
     if (v < g.nlat * g.Vh)
-        trw = update_link<MU, R, HIT1, DLT, false, MEAS>(links, g, par, v, beta, sweep, seed, nhit, att, acc, st);
+        trw = update_link<MU, R, HIT1, DLT, false, MEAS, kStash>(links, g, par, v, beta, sweep, seed, nhit, att, acc,
+                                                                 st);
     count_block(att, acc, counters, blockIdx.x % kCounterSlots);
     if (MEAS) {
         __syncthreads();
@@ -454,8 +456,9 @@ template <int MU, typename R, bool HIT1, bool DLT>
 __global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update_batch(const BatchJob *__restrict__ jobs, const int njobs,
                                                          const long long step, const int par)
 {
+    constexpr bool kStash = kStashBatch<R, DLT>;
     store_t<R> *st = nullptr;
-    if constexpr (kStashOrder<R, DLT>) {
+    if constexpr (kStash) {
         __shared__ store_t<R> stash[kStashSlots * 6 * kBlock];
         st = stash;
     }
@@ -481,8 +484,8 @@ __global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update_batch(const Ba
     const uint64_t sweep = J.sweep0 + (uint64_t)(step - J.admit_step);
     int att = 0, acc = 0;
     if (v < J.g.nlat * J.g.Vh)
-        update_link<MU, R, HIT1, DLT>((store_t<R> *)J.links, J.g, par, v, J.beta, sweep, J.seed, J.nhit, att, acc,
-                                      st);
+        update_link<MU, R, HIT1, DLT, false, false, kStash>((store_t<R> *)J.links, J.g, par, v, J.beta, sweep, J.seed,
+                                                            J.nhit, att, acc, st);
     count_block(att, acc, J.counters, local % kCounterSlots);
 }
 
