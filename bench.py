@@ -157,6 +157,31 @@ def config_rate(L, nlat, precision, beta, sweeps, seed=1, flip_mask=None):
             "plaquette_last": [float(x) for x in plaq[-1]]}
 
 
+def two_coupling_rate(L, beta0, beta1, sweeps, seed=1):
+    """Double-layered torus (flip mask 0x7) with per-layer couplings: link
+    updates/s of `sweeps` sweeps (one untimed sweep first), then the per-layer
+    plaquettes and Polyakov loops."""
+    import torch
+
+    from paper_0904_1179_amd import Lattice
+
+    lat = Lattice(L, nlat=2, precision=64, seed=seed, flip_mask=0x7)
+    lat.start(hot=True)
+    lat.sweep_betas(1, beta0, beta1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.sweep_betas(sweeps, beta0, beta1)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    poly = lat.polyakov()
+    out = {"value": 4 * lat.V * 2 * sweeps / t, "unit": "link updates/s", "sweeps": sweeps, "seconds": t,
+           "beta": [beta0, beta1], "plaquette_per_layer": [float(x) for x in lat.plaquette()[1:]],
+           "polyakov_per_layer": [[float(z.real), float(z.imag)] for z in poly[1:]]}
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(L, beta, seed=1, min_seconds=1.5, max_sweeps=64):
     """The FP64 oracle, as it stands, on the host cores: sweeps of the same
     lattice, one at a time, until min_seconds of wall time have passed."""
@@ -261,11 +286,13 @@ def main():
 
     if not args.no_configs and prec == 64:
         # the other timed workload configurations: a double-layered 2 x 16^4 torus (flip mask 0x7) at beta 5.7,
-        # and 64^4 at beta 6.0 in both precisions (10 sweeps each after one untimed sweep)
+        # 64^4 at beta 6.0 in both precisions (10 sweeps each after one untimed sweep), and the double-layered
+        # torus with per-layer couplings 5.5 / 6.2 (32 sweeps) with its Polyakov loops
         out["configs"] = {
             "dlt_2x16^4_fp64_beta5.7": config_rate(16, 2, 64, 5.7, 32, flip_mask=0x7),
             "64^4_fp64_beta6.0": config_rate(64, 1, 64, 6.0, 10),
-            "64^4_fp32_beta6.0": config_rate(64, 1, 32, 6.0, 10)}
+            "64^4_fp32_beta6.0": config_rate(64, 1, 32, 6.0, 10),
+            "dlt_2x16^4_fp64_beta5.5|6.2": two_coupling_rate(16, 5.5, 6.2, 32)}
 
     if not args.no_serving:
         from paper_0904_1179_amd.serve import run_stream_benchmark

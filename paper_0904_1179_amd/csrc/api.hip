@@ -108,9 +108,15 @@ size_t link_bytes_of(const su3_params *p, const Geom &g)
 
 size_t meas_offset(const Geom &g) { return (size_t)round_up(kOffPartials + 8LL * g.nlat * plaq_blocks(g), 256); }
 
+size_t faces_offset(const Geom &g)
+{
+    return (size_t)round_up((long long)meas_offset(g) + 3 * 8LL * g.nlat * meas_blocks(g), 256);
+}
+
 size_t polyakov_offset(const Geom &g)
 {
-    return (size_t)round_up((long long)meas_offset(g) + 3 * 8LL * meas_blocks(g), 256);
+    const long long faces = g.nlat == 2 ? 2 * 4 * 8LL * face_blocks(g) : 0;
+    return (size_t)round_up((long long)faces_offset(g) + faces, 256);
 }
 
 size_t scratch_bytes_of(const Geom &g)
@@ -269,9 +275,9 @@ su3_status su3_start(su3_ctx *c, int32_t hot)
 namespace {
 
 // enqueue n sweeps (8 pass launches each); arguments already validated.
-// meas != NULL (single torus only): in the last sweep the odd passes of
-// mu = 1, 2, 3 also store their per-workgroup plaquette sums of the planes
-// (nu, mu), nu < mu, in meas[(mu - 1) * meas_blocks .. mu * meas_blocks).
+// meas != NULL: in the last sweep the odd passes of mu = 1, 2, 3 also store
+// their per-workgroup (and per-layer) plaquette sums of the planes (nu, mu),
+// nu < mu, in meas[(mu - 1) * nlat * meas_blocks .. mu * nlat * meas_blocks).
 su3_status enqueue_sweeps(su3_ctx *c, int32_t n, double beta, double *meas = nullptr, const double *betas = nullptr)
 {
     for (int32_t s = 0; s < n; ++s) {
@@ -295,9 +301,9 @@ su3_status enqueue_sweeps(su3_ctx *c, int32_t n, double beta, double *meas = nul
                     e = su3hb::launch_update_twob(c->p.precision, c->links, c->g, mu, par, betas[0], betas[1],
                                                   c->sweep_index, c->p.seed, c->p.nhit, counters_of(c), c->stream);
                 else if (measured)
-                    e = su3hb::launch_update_measured(c->p.precision, c->links, c->g, mu, beta, c->sweep_index,
-                                                      c->p.seed, c->p.nhit, counters_of(c),
-                                                      meas + (size_t)(mu - 1) * su3hb::meas_blocks(c->g), c->stream);
+                    e = su3hb::launch_update_measured(
+                        c->p.precision, c->links, c->g, mu, beta, c->sweep_index, c->p.seed, c->p.nhit,
+                        counters_of(c), meas + (size_t)(mu - 1) * c->g.nlat * su3hb::meas_blocks(c->g), c->stream);
                 else
                     e = su3hb::launch_update(c->p.precision, c->links, c->g, mu, par, beta, c->sweep_index, c->p.seed,
                                              c->p.nhit, counters_of(c), c->stream);
@@ -380,7 +386,6 @@ su3_status su3_sweep_measure(su3_ctx *c, int32_t n, double beta, double *out, si
     const int w = 1 + c->p.nlat;
     if (!out && n > 0) return fail(SU3_EINVAL, "out is NULL");
     if (n_out < (size_t)n * (size_t)w) return fail(SU3_EINVAL, "out must hold n * (1 + nlat) doubles");
-    double *partials = (double *)(c->scratch + kOffPartials);
     double *slots = (double *)(c->scratch + kOffMeasure);
     std::vector<double> h((size_t)kMeasureChunk * 4);
     const double norm = 18.0 * (double)c->V;
@@ -388,17 +393,15 @@ su3_status su3_sweep_measure(su3_ctx *c, int32_t n, double beta, double *out, si
         const int32_t m = std::min<int32_t>(kMeasureChunk, n - done);
         for (int32_t k = 0; k < m; ++k) {
             hipError_t e;
-            if (c->p.nlat == 1) {
-                // the odd passes of mu = 1, 2, 3 measure all six planes; one workgroup adds their partials
-                double *meas = (double *)(c->scratch + meas_offset(c->g));
-                st = enqueue_sweeps(c, 1, beta, meas);
-                if (st != SU3_OK) return st;
-                e = launch_measure_final(meas, c->g, slots + 4 * k, c->stream);
-            } else {
-                st = enqueue_sweeps(c, 1, beta);
-                if (st != SU3_OK) return st;
-                e = launch_plaquette(c->p.precision, c->links, c->g, partials, slots + 4 * k, c->stream);
-            }
+            // the odd passes of mu = 1, 2, 3 measure all six planes; on a double-layered torus one more
+            // kernel finds the plaquettes they file under the wrong layer; one workgroup adds the partials
+            double *meas = (double *)(c->scratch + meas_offset(c->g));
+            double *faces = (double *)(c->scratch + faces_offset(c->g));
+            st = enqueue_sweeps(c, 1, beta, meas);
+            if (st != SU3_OK) return st;
+            e = hipSuccess;
+            if (c->p.nlat == 2) e = launch_plaq_faces(c->p.precision, c->links, c->g, faces, c->stream);
+            if (e == hipSuccess) e = launch_measure_final(meas, faces, c->g, slots + 4 * k, c->stream);
             if (e != hipSuccess) return hip_fail(e, "plaquette kernels");
         }
         hipError_t e = hipMemcpyAsync(h.data(), slots, sizeof(double) * 4 * m, hipMemcpyDeviceToHost, c->stream);

@@ -14,6 +14,8 @@
 // Kennedy-Pendleton sampling, reunitarises in FP64 and writes the link back.
 // Links of one pass share no plaquette, so threads never read what another
 // thread of the same pass writes.
+#include <algorithm>
+
 #include "launch.h"
 
 namespace su3hb {
@@ -353,9 +355,10 @@ __device__ __forceinline__ int pass_tile(int par)
     return par ? (int)gridDim.x - 1 - t : t;
 }
 
-// One checkerboard pass.  MEAS: also store, per workgroup, the sum of
-// Re Tr(U_new A) over its links (used on the last pass of a sweep, where it
-// is the sum of the final plaquettes in the planes (nu, MU), nu < MU).
+// One checkerboard pass.  MEAS (odd passes of MU = 1, 2, 3): also store, per
+// workgroup, the sum over its links of the final plaquettes of the planes
+// (nu, MU), nu < MU, that update_link returns; on a double-layered torus
+// one sum per layer of the updated site.
 template <int MU, typename R, bool HIT1, bool DLT, bool MEAS = false>
 __global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update(store_t<R> *__restrict__ links, const Geom g, const int par,
                                                    const double beta, const uint64_t sweep, const uint64_t seed,
@@ -377,8 +380,20 @@ __global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update(store_t<R> *__
     count_block(att, acc, counters, blockIdx.x % kCounterSlots);
     if (MEAS) {
         __syncthreads();
-        const double b = block_sum(trw);
-        if (threadIdx.x == 0) meas[blockIdx.x] = b;
+        if constexpr (DLT) {
+            // per layer of the updated site: meas[2 b + layer]
+            const bool l1 = v >= g.Vh;
+            const double b0 = block_sum(l1 ? 0.0 : trw);
+            __syncthreads();
+            const double b1 = block_sum(l1 ? trw : 0.0);
+            if (threadIdx.x == 0) {
+                meas[2 * blockIdx.x] = b0;
+                meas[2 * blockIdx.x + 1] = b1;
+            }
+        } else {
+            const double b = block_sum(trw);
+            if (threadIdx.x == 0) meas[blockIdx.x] = b;
+        }
     }
 }
 
@@ -637,6 +652,97 @@ __global__ __launch_bounds__(kBlock) void k_plaq_partial(const store_t<R> *__res
     if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = bs;
 }
 
+// Double-layered torus, fused measurement: the measured odd pass of MU files
+// the plaquette of the lower staple term of site x (based at y = x - nu) under
+// the layer of x.  y lies in the other layer exactly when the step crosses a
+// flipped boundary of direction nu, i.e. y_nu = L_nu - 1, y even.  This kernel
+// sums those plaquettes, planes (nu, mu) with mu > nu, per layer of y, so that
+// the per-layer sums can be moved to the right layer.  Grid (nblk, 4):
+// blockIdx.y = nu; thread q enumerates the face y_nu = L_nu - 1 (both
+// parities; odd sites contribute nothing); partials[2 (nu nblk + b) + layer].
+template <int NU, typename R>
+__device__ __forceinline__ void face_site(const store_t<R> *__restrict__ links, const Geom &g, long long q, double &s0,
+                                          double &s1)
+{
+    int y[4];
+    long long r = q;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        if (d == NU) continue;
+        y[d] = (int)(r % g.L[d]);
+        r /= g.L[d];
+    }
+    const int layer = (int)r;
+    y[NU] = g.L[NU] - 1;
+    if ((y[0] + y[1] + y[2] + y[3]) & 1) return;
+    const int n = layer * g.Vh + (lex_of(g, y) >> 1);
+    double t = 0.0;
+    if constexpr (NU < 1) t += plaq_plane<NU, 1, R, true>(links, g, y, layer, 0, n);
+    if constexpr (NU < 2) t += plaq_plane<NU, 2, R, true>(links, g, y, layer, 0, n);
+    if constexpr (NU < 3) t += plaq_plane<NU, 3, R, true>(links, g, y, layer, 0, n);
+    if (layer)
+        s1 += t;
+    else
+        s0 += t;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_plaq_faces(const store_t<R> *__restrict__ links, const Geom g,
+                                                       double *__restrict__ partials)
+{
+    const int nu = blockIdx.y;
+    double s0 = 0.0, s1 = 0.0;
+    const long long nface = (long long)g.nlat * (2LL * g.Vh / g.L[nu]);
+    const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (((g.flip >> nu) & 1) && q < nface) {
+        switch (nu) {
+        case 0: face_site<0, R>(links, g, q, s0, s1); break;
+        case 1: face_site<1, R>(links, g, q, s0, s1); break;
+        case 2: face_site<2, R>(links, g, q, s0, s1); break;
+        default: break;  // planes (3, mu) with mu > 3 do not exist
+        }
+    }
+    const double b0 = block_sum(s0);
+    __syncthreads();
+    const double b1 = block_sum(s1);
+    if (threadIdx.x == 0) {
+        const size_t k = (size_t)nu * gridDim.x + blockIdx.x;
+        partials[2 * k] = b0;
+        partials[2 * k + 1] = b1;
+    }
+}
+
+// Double-layered torus: per-layer plaquette sums of a measured sweep.  meas:
+// nmeas pairs (T_0, T_1) of the three measured passes; faces: nfaces pairs
+// (C_0, C_1).  sums[1 + l] = T_l + C_l - C_{1-l}, sums[0] = sums[1] + sums[2].
+__global__ __launch_bounds__(kBlock) void k_measure_final_dlt(const double *__restrict__ meas, int nmeas,
+                                                              const double *__restrict__ faces, int nfaces,
+                                                              double *__restrict__ sums)
+{
+    double t0 = 0.0, t1 = 0.0, c0 = 0.0, c1 = 0.0;
+    for (int k = threadIdx.x; k < nmeas; k += kBlock) {
+        t0 += meas[2 * k];
+        t1 += meas[2 * k + 1];
+    }
+    for (int k = threadIdx.x; k < nfaces; k += kBlock) {
+        c0 += faces[2 * k];
+        c1 += faces[2 * k + 1];
+    }
+    const double T0 = block_sum(t0);
+    __syncthreads();
+    const double T1 = block_sum(t1);
+    __syncthreads();
+    const double C0 = block_sum(c0);
+    __syncthreads();
+    const double C1 = block_sum(c1);
+    if (threadIdx.x == 0) {
+        const double p0 = T0 + C0 - C1, p1 = T1 + C1 - C0;
+        sums[0] = p0 + p1;
+        sums[1] = p0;
+        sums[2] = p1;
+    }
+}
+
 // sums[1 + l] = sum over the partials of layer l; sums[0] = sum over layers
 __global__ __launch_bounds__(kBlock) void k_plaq_final(const double *__restrict__ partials, int nblk, int nlat,
                                                        double *__restrict__ sums)
@@ -797,13 +903,20 @@ template <int MU, typename R>
 static void update_meas_launch(store_t<R> *links, const Geom &g, double beta, uint64_t sweep, uint64_t seed, int nhit,
                                unsigned long long *counters, double *meas, hipStream_t s)
 {
-    const dim3 grid(blocks_for((long long)g.Vh));
-    if (nhit == 1)
+    const dim3 grid(meas_blocks(g));
+    const bool dlt = g.nlat == 2;
+    if (nhit == 1 && !dlt)
         k_update<MU, R, true, false, true><<<grid, kBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit, counters,
                                                                     meas);
-    else
+    else if (nhit == 1)
+        k_update<MU, R, true, true, true><<<grid, kBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit, counters,
+                                                                   meas);
+    else if (!dlt)
         k_update<MU, R, false, false, true><<<grid, kBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit, counters,
                                                                      meas);
+    else
+        k_update<MU, R, false, true, true><<<grid, kBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit, counters,
+                                                                    meas);
 }
 
 template <typename R>
@@ -817,7 +930,23 @@ static void update_meas_dispatch(store_t<R> *links, const Geom &g, int mu, doubl
     }
 }
 
-int meas_blocks(const Geom &g) { return (int)blocks_for((long long)g.Vh); }
+int meas_blocks(const Geom &g) { return (int)blocks_for((long long)g.nlat * g.Vh); }
+
+int face_blocks(const Geom &g)
+{
+    const int lmin = std::min(std::min(g.L[0], g.L[1]), g.L[2]);
+    return (int)blocks_for((long long)g.nlat * (2LL * g.Vh / lmin));
+}
+
+hipError_t launch_plaq_faces(int precision, const void *links, const Geom &g, double *partials, hipStream_t s)
+{
+    const dim3 grid(face_blocks(g), 4);
+    if (precision == 64)
+        k_plaq_faces<double><<<grid, kBlock, 0, s>>>((const double2 *)links, g, partials);
+    else
+        k_plaq_faces<float><<<grid, kBlock, 0, s>>>((const float2 *)links, g, partials);
+    return hipGetLastError();
+}
 
 hipError_t launch_update_measured(int precision, void *links, const Geom &g, int mu, double beta, uint64_t sweep,
                                   uint64_t seed, int nhit, unsigned long long *counters, double *meas, hipStream_t s)
@@ -830,9 +959,12 @@ hipError_t launch_update_measured(int precision, void *links, const Geom &g, int
     return hipGetLastError();
 }
 
-hipError_t launch_measure_final(const double *meas, const Geom &g, double *sums, hipStream_t s)
+hipError_t launch_measure_final(const double *meas, const double *faces, const Geom &g, double *sums, hipStream_t s)
 {
-    k_sum_partials<<<1, kBlock, 0, s>>>(meas, 3 * meas_blocks(g), sums);
+    if (g.nlat == 1)
+        k_sum_partials<<<1, kBlock, 0, s>>>(meas, 3 * meas_blocks(g), sums);
+    else
+        k_measure_final_dlt<<<1, kBlock, 0, s>>>(meas, 3 * meas_blocks(g), faces, 4 * face_blocks(g), sums);
     return hipGetLastError();
 }
 

@@ -37,15 +37,20 @@ hipError_t launch_update_batch(int precision, bool hit1, bool dlt, const BatchJo
                                long long step, int mu, int par, hipStream_t s);
 hipError_t launch_plaquette(int precision, const void *links, const Geom &g, double *partials, double *sums,
                             hipStream_t s);
-// Single torus: the odd pass of mu (1, 2 or 3) that also stores, per
-// workgroup, the sum of its final plaquettes in the planes (nu, mu), nu < mu,
-// into meas[0 .. meas_blocks(g)).  With the three passes writing consecutive
-// slices of 3 * meas_blocks(g) doubles, launch_measure_final adds them up into
-// sums[0] = sums[1] (the plaquette sum over all six planes).
+// The odd pass of mu (1, 2 or 3) that also stores, per workgroup, the sum of
+// its final plaquettes in the planes (nu, mu), nu < mu: meas[b] on a single
+// torus, meas[2 b + layer of the updated site] on a double-layered torus, b <
+// meas_blocks(g).  The three passes write consecutive slices of
+// nlat * meas_blocks(g) doubles.  On a double-layered torus launch_plaq_faces
+// then sums the plaquettes those passes file under the wrong layer
+// (2 * 4 * face_blocks(g) doubles).  launch_measure_final adds everything up
+// into sums[0] (total) and sums[1 + l] (layer l).
 int meas_blocks(const Geom &g);
+int face_blocks(const Geom &g);
 hipError_t launch_update_measured(int precision, void *links, const Geom &g, int mu, double beta, uint64_t sweep,
                                   uint64_t seed, int nhit, unsigned long long *counters, double *meas, hipStream_t s);
-hipError_t launch_measure_final(const double *meas, const Geom &g, double *sums, hipStream_t s);
+hipError_t launch_plaq_faces(int precision, const void *links, const Geom &g, double *partials, hipStream_t s);
+hipError_t launch_measure_final(const double *meas, const double *faces, const Geom &g, double *sums, hipStream_t s);
 // double-layered torus with per-layer couplings (a plaquette takes its base site's layer coupling)
 hipError_t launch_update_twob(int precision, void *links, const Geom &g, int mu, int par, double beta0,
                               double beta1, uint64_t sweep, uint64_t seed, int nhit, unsigned long long *counters,

@@ -273,11 +273,11 @@ def test_stream_copy_and_profile(hb):
     assert n == 0 and ms == 0
 
 
-@pytest.mark.parametrize("nlat", [1, 2])
-def test_sweep_measure_matches_sweep_then_plaquette(hb, nlat):
+@pytest.mark.parametrize("nlat,flip", [(1, None), (2, 0x7), (2, 0xF), (2, 0x0)])
+def test_sweep_measure_matches_sweep_then_plaquette(hb, nlat, flip):
     L = (4, 4, 6, 4)
-    a = hb.Lattice(L, nlat=nlat, seed=9)
-    b = hb.Lattice(L, nlat=nlat, seed=9)
+    a = hb.Lattice(L, nlat=nlat, flip_mask=flip, seed=9)
+    b = hb.Lattice(L, nlat=nlat, flip_mask=flip, seed=9)
     a.start(True)
     b.start(True)
     got = a.sweep_measure(300, 5.7)  # crosses the 256-sweep chunk
@@ -285,9 +285,9 @@ def test_sweep_measure_matches_sweep_then_plaquette(hb, nlat):
     for k in range(300):
         b.sweep(1, 5.7)
         if k in (0, 1, 255, 256, 299):
-            # single torus: fused measurement, equal up to rounding; DLT: the same kernel, bitwise
-            tol = 1e-13 if nlat == 1 else 0.0
-            assert np.abs(got[k] - b.plaquette()).max() <= tol
+            # measured inside the passes (DLT: plus the boundary-plaquette correction per layer):
+            # the same plaquettes summed in another order
+            assert np.abs(got[k] - b.plaquette()).max() <= 1e-13
     assert np.array_equal(a.get_links(), b.get_links())
     sa, sb = a.counters(), b.counters()
     assert sa == sb
@@ -316,3 +316,18 @@ def test_sweep_measure_against_oracle(hb, precision):
     print(f"FP32 vs FP64 chain: max rel. error before onset {rel[:onset].max():.2e}, onset at sweep {onset + 1}")
     assert onset >= 4
     assert np.all(np.abs(got[:, 0] - ref) <= 2e-3)
+
+
+@pytest.mark.parametrize("L,flip", [((4, 4, 4, 6), 0x7), ((4, 6, 4, 4), 0xF)])
+def test_dlt_sweep_measure_per_layer_against_oracle(hb, L, flip):
+    """The fused measurement of a double-layered torus (passes + boundary
+    plaquettes moved to their base site's layer) against the oracle's per-layer
+    plaquette after every sweep."""
+    lat = hb.Lattice(L, nlat=2, flip_mask=flip, seed=23)
+    ref = _oracle(L, 2, flip, seed=23)
+    lat.start(True)
+    ref.start(True)
+    got = lat.sweep_measure(4, 5.7)
+    for k in range(4):
+        ref.sweep(1, 5.7)
+        assert np.abs(got[k] - ref.plaquette()).max() < 1e-12, (k, got[k], ref.plaquette())
