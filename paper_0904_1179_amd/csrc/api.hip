@@ -75,6 +75,45 @@ su3_status check_params(const su3_params *p)
     return SU3_OK;
 }
 
+// Domains of the pass order (the (x1, x2) cross-section cut into w1 x w2
+// pieces, each swept along x3).  A link on a domain's rim is read by two
+// XCDs, each from HBM, so the choice takes the fewest rim links, the sum of
+// 1/w over the directions that are cut, among the widths that
+//  * give every XCD whole domains: nd * nlat a multiple of 8, nd = (L1/w1)(L2/w2);
+//  * keep one x3 slab of a domain within 16 workgroups (L0/2 w1 w2 <= 4096
+//    updates), so that the links around it are re-read while still in L2;
+//  * keep the lanes of a wave on whole 16-link tiles: L0/2 w1 a multiple of 16,
+//    or w1 = L1.
+// Ties go to the wider w1 (longer runs of consecutive links).  Without such
+// widths the rule keeps w1 = L1 and the largest w2 <= L2/8.
+void pick_domains(const int32_t L[4], int nlat, int &w1, int &w2)
+{
+    const int l0h = L[0] / 2;
+    double best = 1e30;
+    w1 = L[1];
+    w2 = 0;
+    for (int a = L[1]; a >= 1; --a) {
+        if (L[1] % a || (a != L[1] && (l0h * a) % 16)) continue;
+        for (int b = L[2]; b >= 1; --b) {
+            if (L[2] % b) continue;
+            const long long nd = (long long)(L[1] / a) * (L[2] / b) * nlat;
+            if (nd % 8 || (long long)l0h * a * b > 16 * kBlock) continue;
+            const double rim = (a < L[1] ? 1.0 / a : 0.0) + (b < L[2] ? 1.0 / b : 0.0);
+            if (rim < best - 1e-12) {
+                best = rim;
+                w1 = a;
+                w2 = b;
+            }
+        }
+    }
+    if (w2 == 0) {
+        w1 = L[1];
+        w2 = 1;
+        for (int b = 1; b <= L[2] / 8; ++b)
+            if (L[2] % b == 0) w2 = b;
+    }
+}
+
 Geom make_geom(const su3_params *p)
 {
     su3hb::Geom g;
@@ -87,16 +126,15 @@ Geom make_geom(const su3_params *p)
     // power-of-two spacing, so equal positions in different blocks do not all
     // fall in the same L2 channel and set
     g.stride = round_up((long long)p->nlat * (V / 2), 64) + 64;
-    // pass order: x2 cut into chunks of w2 planes, the largest divisor of L2
-    // not above L2/8 (one chunk per XCD when L2 is a multiple of 8)
-    g.w2 = 1;
-    for (int w = 1; w <= p->L[2] / 8; ++w)
-        if (p->L[2] % w == 0) g.w2 = w;
+    pick_domains(p->L, p->nlat, g.w1, g.w2);
+    g.nd1 = p->L[1] / g.w1;
     g.dl0h = su3hb::make_fastdiv((uint32_t)(p->L[0] / 2));
     g.dl1 = su3hb::make_fastdiv((uint32_t)p->L[1]);
     g.dl2 = su3hb::make_fastdiv((uint32_t)p->L[2]);
     g.dl3 = su3hb::make_fastdiv((uint32_t)p->L[3]);
+    g.dw1 = su3hb::make_fastdiv((uint32_t)g.w1);
     g.dw2 = su3hb::make_fastdiv((uint32_t)g.w2);
+    g.dnd1 = su3hb::make_fastdiv((uint32_t)g.nd1);
     return g;
 }
 

@@ -268,6 +268,23 @@ struct U64x4 {
     uint64_t w[4];
 };
 
+// Full 128-bit product a m, m a compile-time constant, from 32-bit limbs
+// a = a1 2^32 + a0, m = m1 2^32 + m0:
+//   t = a0 m1 + hi(a0 m0),  u = a1 m0 + lo(t),
+//   a m = lo(a0 m0) + 2^32 lo(u) + 2^64 (a1 m1 + hi(t) + hi(u)),
+// where no partial sum overflows 64 bits.  Four 32x32+64 multiply-adds; the
+// separate low product and high product would form the cross terms twice.
+template <uint64_t M> __device__ __forceinline__ void mulhilo64(uint64_t a, uint64_t &lo, uint64_t &hi)
+{
+    constexpr uint32_t m0 = (uint32_t)M, m1 = (uint32_t)(M >> 32);
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+    const uint64_t p = (uint64_t)a0 * m0;
+    const uint64_t t = (uint64_t)a0 * m1 + (p >> 32);
+    const uint64_t u = (uint64_t)a1 * m0 + (uint32_t)t;
+    lo = (u << 32) | (uint32_t)p;
+    hi = (uint64_t)a1 * m1 + ((t >> 32) + (u >> 32));
+}
+
 __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
                                                uint64_t k1)
 {
@@ -275,8 +292,9 @@ __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
     constexpr uint64_t kBump0 = 0x9E3779B97F4A7C15ull, kBump1 = 0xBB67AE8584CAA73Bull;
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint64_t lo_a = kMul0 * c0, hi_a = __umul64hi(kMul0, c0);
-        const uint64_t lo_b = kMul1 * c2, hi_b = __umul64hi(kMul1, c2);
+        uint64_t lo_a, hi_a, lo_b, hi_b;
+        mulhilo64<kMul0>(c0, lo_a, hi_a);
+        mulhilo64<kMul1>(c2, lo_b, hi_b);
         c0 = hi_b ^ c1 ^ k0;
         c1 = lo_b;
         c2 = hi_a ^ c3 ^ k1;
@@ -351,8 +369,9 @@ struct Geom {
     int nlat;
     unsigned flip;      // layer-switch mask, 0 on a single torus
     long long stride;   // links per (direction, parity) block (>= nlat * Vh, multiple of 64)
-    int w2;             // chunk width of the pass order (divides L2)
-    FastDiv dl0h, dl1, dl2, dl3, dw2;  // division by L0/2, L1, L2, L3, w2
+    int w1, w2;         // domain widths of the pass order (divide L1, L2)
+    int nd1;            // L1 / w1
+    FastDiv dl0h, dl1, dl2, dl3, dw1, dw2, dnd1;  // division by L0/2, L1, L2, L3, w1, w2, nd1
 };
 
 // Coordinates of the site with parity `par` and half-index i.
@@ -409,28 +428,39 @@ __device__ __forceinline__ int nbr_elem(const Geom &g, const int x[4], int layer
     return DLT ? ly * g.Vh + e : e;
 }
 
-// Processing order of one pass.  Thread v of a layer handles the site with
-// half-index i(v): v = x0h + (L0/2)(x1 + L1(x2' + w2 (x3 + L3 c))) with
-// x2 = c w2 + x2', i.e. the lattice is cut into L2/w2 chunks of w2 planes in
-// the x2 direction and each chunk is swept along x3.  Together with xcd_tile
-// each XCD owns whole chunks, so a link is re-read while it is still in that
-// XCD's L2.  Lanes of a wave still cover consecutive x0, so loads stay
-// coalesced.  w2 must divide L2.
-__device__ __forceinline__ int chunk_order(const Geom &g, int v)
+// Processing order of one pass.  The (x1, x2) cross-section is cut into
+// domains of w1 x w2 sites, numbered d = c1 + nd1 c2 (x1 = c1 w1 + x1',
+// x2 = c2 w2 + x2'), and each domain is swept along x3:
+//   v = x0h + (L0/2)(x1' + w1 (x2' + w2 (x3 + L3 d))).
+// Together with xcd_tile each XCD owns whole domains, so a link is re-read
+// while it is still in that XCD's L2, and square-ish domains keep the links
+// that two XCDs both read (the domain's rim) few.  Lanes of a wave still
+// cover consecutive x0, so loads stay coalesced.  Returns the half-index i of
+// thread v's site and fills its coordinates (x0 for parity par).
+__device__ __forceinline__ int order_site(const Geom &g, int par, int v, int x[4])
 {
-    const int l0h = g.L[0] >> 1, w2 = g.w2;
+    const int l0h = g.L[0] >> 1;
     int r = div_by(v, g.dl0h);
     const int x0h = v - r * l0h;
-    int q = div_by(r, g.dl1);
-    const int x1 = r - q * g.L[1];
+    int q = div_by(r, g.dw1);
+    const int x1p = r - q * g.w1;
     r = q;
     q = div_by(r, g.dw2);
-    const int x2p = r - q * w2;
+    const int x2p = r - q * g.w2;
     r = q;
     q = div_by(r, g.dl3);
-    const int x3 = r - q * g.L[3];
-    const int x2 = q * w2 + x2p;
-    return x0h + l0h * (x1 + g.L[1] * (x2 + g.L[2] * x3));
+    x[3] = r - q * g.L[3];
+    r = q;
+    q = div_by(r, g.dnd1);
+    x[1] = (r - q * g.nd1) * g.w1 + x1p;
+    x[2] = q * g.w2 + x2p;
+    x[0] = 2 * x0h + ((par + x[1] + x[2] + x[3]) & 1);
+    return x0h + l0h * (x[1] + g.L[1] * (x[2] + g.L[2] * x[3]));
+}
+__device__ __forceinline__ int chunk_order(const Geom &g, int v)
+{
+    int x[4];
+    return order_site(g, 0, v, x);
 }
 
 // Link storage.  A link is stored as its rows 0 and 1, the six complex

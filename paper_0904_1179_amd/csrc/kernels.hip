@@ -240,10 +240,9 @@ __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, co
     constexpr int N1 = MU <= 1 ? 2 : 1;
     constexpr int N2 = MU <= 2 ? 3 : 2;
     const int layer = DLT && v >= g.Vh ? 1 : 0;
-    const int i = chunk_order(g, v - layer * g.Vh);
-    const int n = layer * g.Vh + i;
     int x[4];
-    site_coords(g, par, i, x);
+    const int i = order_site(g, par, v - layer * g.Vh, x);
+    const int n = layer * g.Vh + i;
     M3<R> A, S;
     set_zero(A);
     __builtin_amdgcn_s_setprio(1);  // gathering the staple: issue loads ahead of waves in the heat bath

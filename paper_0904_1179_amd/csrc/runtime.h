@@ -28,6 +28,7 @@ constexpr size_t kOffMeasure = kOffSums + 256;
 constexpr size_t kOffPartials = kOffMeasure + 32 * (size_t)kMeasureChunk;
 
 su3_status check_params(const su3_params *p);
+void pick_domains(const int32_t L[4], int nlat, int &w1, int &w2);
 Geom make_geom(const su3_params *p);
 size_t link_bytes_of(const su3_params *p, const Geom &g);
 size_t scratch_bytes_of(const Geom &g);
