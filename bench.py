@@ -82,9 +82,8 @@ def run_gpu(L, precision, steps, warmup, beta, seed=1):
 
     lat = Lattice(L, nlat=1, precision=precision, seed=seed)
     lat.start(hot=True)
-    for _ in range(warmup):
-        lat.sweep(1, beta)
-        lat.plaquette()
+    if warmup > 0:
+        lat.sweep_measure(warmup, beta)
     torch.cuda.synchronize()
     lat.profile(True)
     lat.profile_read()
@@ -95,9 +94,11 @@ def run_gpu(L, precision, steps, warmup, beta, seed=1):
     t1 = time.perf_counter()
     pass_ms, passes = lat.profile_read()
     lat.profile(False)
+    # the last fused measurement against the full plaquette kernel (after the timed region)
+    full = float(lat.plaquette()[0])
     V = L ** 4
     return {"seconds": t1 - t0, "updates": 4 * V * steps, "pass_ms": pass_ms / max(passes, 1), "passes": passes,
-            "plaquette": plaq, "lattice": lat}
+            "plaquette": plaq, "plaquette_full_kernel": full, "lattice": lat}
 
 
 def copy_probe_gbs(nbytes=1 << 30, reps=10):
@@ -223,7 +224,9 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=3)
+    # the first ~60 sweeps of a process run up to 15% slower while the GPU warms
+    # up (a second lattice in the same process runs at full speed at once)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--L", type=int, default=32)
     ap.add_argument("--beta", type=float, default=5.7)
     ap.add_argument("--precision", type=int, default=64, choices=(64, 32))
@@ -271,6 +274,7 @@ def main():
                       "precision": prec, "parallelism": "single GPU"},
            "us_per_update_gpu": main_run["seconds"] / main_run["updates"] * 1e6,
            "plaquette_last": main_run["plaquette"][-1],
+           "plaquette_last_full_kernel": main_run["plaquette_full_kernel"],
            "roofline": roofline}
 
     if not args.no_fp32 and prec == 64:
