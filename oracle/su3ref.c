@@ -560,6 +560,20 @@ su3ref_lattice *su3ref_create(const su3ref_params *p)
     return lat;
 }
 
+/* Geometry only: no link storage (links is NULL).  Only the index functions
+   (volume, parity, neighbor, staple_lids) may be called on it; they serve
+   checks of single links of lattices too large to hold on the host. */
+su3ref_lattice *su3ref_create_geometry(const su3ref_params *p)
+{
+    if (su3ref_check_params(p) != 0) return NULL;
+    su3ref_lattice *lat = (su3ref_lattice *)calloc(1, sizeof *lat);
+    if (!lat) return NULL;
+    lat->p = *p;
+    lat->V = (int64_t)p->L[0] * p->L[1] * p->L[2] * p->L[3];
+    lat->links = NULL;
+    return lat;
+}
+
 void su3ref_destroy(su3ref_lattice *lat)
 {
     if (!lat) return;

@@ -42,6 +42,8 @@ int su3ref_check_params(const su3ref_params *p);
 
 /* Allocate a lattice (host memory).  NULL on invalid parameters. */
 su3ref_lattice *su3ref_create(const su3ref_params *p);
+/* geometry only (no links): index functions only */
+su3ref_lattice *su3ref_create_geometry(const su3ref_params *p);
 void su3ref_destroy(su3ref_lattice *lat);
 
 /* Number of doubles in the canonical link array (18 * 4 * V * nlat). */

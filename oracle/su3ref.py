@@ -33,6 +33,7 @@ def load():
     sig = {
         "su3ref_check_params": (C.c_int, [C.POINTER(Params)]),
         "su3ref_create": (vp, [C.POINTER(Params)]),
+        "su3ref_create_geometry": (vp, [C.POINTER(Params)]),
         "su3ref_destroy": (None, [vp]),
         "su3ref_n_doubles": (i64, [vp]),
         "su3ref_links": (dp, [vp]),
@@ -167,6 +168,39 @@ def single_link_chain(U, A, beta, seed, nsteps, nhit=1):
 # ---------------------------------------------------------------------------
 # lattice
 # ---------------------------------------------------------------------------
+
+class Geometry:
+    """The oracle's site and link indexing for a lattice it does not hold:
+    parity, neighbours and staple link ids only, at any size the parameters
+    allow."""
+
+    def __init__(self, L, nlat=1, flip_mask=None):
+        self.params = make_params(L, nlat, flip_mask, 1, 1)
+        lib_ = load()
+        self._h = lib_.su3ref_create_geometry(C.byref(self.params))
+        if not self._h:
+            raise ValueError("invalid oracle parameters")
+        self.nlat = int(nlat)
+        self.L = tuple(self.params.L)
+        self.V = int(lib_.su3ref_volume(self._h))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.su3ref_destroy(h)
+            self._h = None
+
+    def parity(self, site):
+        return int(_lib.su3ref_parity(self._h, int(site)))
+
+    def neighbor(self, site, mu, d):
+        return int(_lib.su3ref_neighbor(self._h, int(site), int(mu), int(d)))
+
+    def staple_lids(self, site, mu):
+        out = np.zeros(18, dtype=np.int64)
+        _lib.su3ref_staple_lids(self._h, int(site), int(mu), _p(out, C.c_int64))
+        return out
+
 
 class Oracle:
     """A whole lattice held by the CPU oracle."""

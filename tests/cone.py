@@ -15,7 +15,7 @@ from oracle import su3ref
 
 class FirstSweepCone:
     def __init__(self, L, nlat=1, flip_mask=None, seed=1, beta=5.7, nhit=1, hot=True):
-        self.geo = su3ref.Oracle(L, nlat=nlat, flip_mask=flip_mask, nhit=nhit, seed=seed)
+        self.geo = su3ref.Geometry(L, nlat=nlat, flip_mask=flip_mask)
         self.seed, self.beta, self.nhit, self.hot = seed, beta, nhit, hot
         self.memo = {}
 

@@ -142,3 +142,42 @@ def test_64_config_beta6_sampled(hb):
         if precision == 64:
             assert dev.max() < tol
         del lat
+
+
+def test_size_limit_fp32_sampled(hb):
+    """The largest lattice the library accepts, 2^30 sites (256 x 256 x 128 x
+    128, FP32 links: 206 GB of HBM; link offsets far beyond 2^31 elements):
+    one sweep from a hot start, sampled links against the FP64 oracle computed
+    link by link, exact attempt count, unitarity and the whole-lattice
+    plaquette."""
+    import torch
+    from cone import FirstSweepCone, sample_lids
+    from oracle import su3ref
+
+    L = (256, 256, 128, 128)
+    V = 1 << 30
+    p = hb.make_params(L, precision=32, seed=1)
+    nl, ns = hb.su3_footprint(p)
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < nl + ns + (4 << 30):
+        pytest.skip(f"needs {(nl + ns) / 1e9:.0f} GB of free device memory, {free / 1e9:.0f} GB free")
+    _say(f"size limit: {L} FP32, {nl / 1e9:.1f} GB of links")
+    lat = hb.Lattice(L, precision=32, seed=1)
+    lat.start(True)
+    lat.sweep(1, 5.7)
+    sweeps, att, acc = lat.counters()
+    assert sweeps == 1 and att == 3 * 4 * V and 0 < acc <= att
+    lids = sample_lids(4 * V, 32, seed=30)
+    got = su3ref.to_complex(lat.link_sample(lids))
+    cone = FirstSweepCone(L, seed=1, beta=5.7)
+    dev = np.array([np.abs(got[k] - cone.value(l)).max() for k, l in enumerate(lids)])
+    _say(f"  sampled links: median dev {np.median(dev):.1e}, max {dev.max():.1e}")
+    assert np.median(dev) < 1e-4
+    assert (dev < 1e-4).mean() >= 0.9
+    assert np.abs(got @ got.conj().transpose(0, 2, 1) - np.eye(3)).max() < 1e-6
+    plaq = lat.plaquette()
+    _say(f"  plaquette {plaq[0]:.6f}")
+    assert 0.2 < plaq[0] < 0.8
+    del lat
+    torch.cuda.empty_cache()
