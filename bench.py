@@ -101,6 +101,28 @@ def run_gpu(L, precision, steps, warmup, beta, seed=1):
             "plaquette": plaq, "plaquette_full_kernel": full, "lattice": lat}
 
 
+def repeat_rates(lat, beta, repeats=10, sweeps=10):
+    """Spread of the sweep rate: `repeats` fresh hot starts of the same
+    lattice, each followed by `sweeps` sweeps timed with HIP events on the
+    lattice's stream (su3_sweep, no measurement)."""
+    import numpy as np
+    import torch
+
+    rates = []
+    for _ in range(repeats):
+        lat.start(hot=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(lat.stream)
+        lat.sweep(sweeps, beta)
+        e1.record(lat.stream)
+        e1.synchronize()
+        rates.append(4 * lat.V * lat.nlat * sweeps / (e0.elapsed_time(e1) * 1e-3))
+    r = np.sort(np.array(rates))
+    return {"repeats": repeats, "sweeps_each": sweeps, "median": float(np.median(r)),
+            "p10": float(np.percentile(r, 10)), "p90": float(np.percentile(r, 90)), "unit": "link updates/s",
+            "timing": "HIP events around su3_sweep on the lattice's stream, each from a fresh hot start"}
+
+
 def copy_probe_gbs(nbytes=1 << 30, reps=10):
     import torch
 
@@ -262,6 +284,7 @@ def main():
                 "launches_timed": main_run["passes"]}
     if not args.no_copy_probe:
         roofline["copy_probe_gbs"] = round(copy_probe_gbs(), 1)
+    spread = repeat_rates(main_run["lattice"], beta)
     del main_run["lattice"]
 
     out = {"metric": "SU(3) link updates/sec at 32^4 (FP64 checkerboard heat-bath sweep + plaquette)",
@@ -275,6 +298,7 @@ def main():
            "us_per_update_gpu": main_run["seconds"] / main_run["updates"] * 1e6,
            "plaquette_last": main_run["plaquette"][-1],
            "plaquette_last_full_kernel": main_run["plaquette_full_kernel"],
+           "sweep_rate_spread": spread,
            "roofline": roofline}
 
     if not args.no_fp32 and prec == 64:

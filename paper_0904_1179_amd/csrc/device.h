@@ -457,7 +457,7 @@ __device__ __forceinline__ int order_site(const Geom &g, int par, int v, int x[4
     x[0] = 2 * x0h + ((par + x[1] + x[2] + x[3]) & 1);
     return x0h + l0h * (x[1] + g.L[1] * (x[2] + g.L[2] * x[3]));
 }
-__device__ __forceinline__ int chunk_order(const Geom &g, int v)
+__device__ __forceinline__ int order_index(const Geom &g, int v)
 {
     int x[4];
     return order_site(g, 0, v, x);

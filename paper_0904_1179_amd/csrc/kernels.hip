@@ -629,7 +629,7 @@ __device__ __forceinline__ double plaq_site(const store_t<R> *__restrict__ links
 // Grid (nblk, nlat).  Workgroup b (XCD-remapped) sums the contiguous run of
 // tiles [b T, (b+1) T) of its layer in the pass order; thread v of a tile
 // takes both sites with half-index i(v) (x0 neighbours), so the links of both
-// parities around a chunk are read while they are in that XCD's L2.  Fixed
+// parities around a domain are read while they are in that XCD's L2.  Fixed
 // per-thread order, wave shuffles and a fixed per-block order: the sum is
 // bitwise reproducible.
 template <typename R, bool DLT>
@@ -642,7 +642,7 @@ __global__ __launch_bounds__(kBlock) void k_plaq_partial(const store_t<R> *__res
     for (int t = 0; t < tiles_per_block; ++t) {
         const int v = (b * tiles_per_block + t) * kBlock + threadIdx.x;
         if (v < g.Vh) {
-            const int i = chunk_order(g, v);
+            const int i = order_index(g, v);
             s += plaq_site<R, DLT>(links, g, layer, 0, i);
             s += plaq_site<R, DLT>(links, g, layer, 1, i);
         }
