@@ -215,21 +215,22 @@ template <typename R> __device__ __forceinline__ M3<R> from_raw(const Raw12<R> &
 // the occupancy it is meant to preserve): stash_fence() between the writes
 // and the reads is a compiler-only memory barrier, so the compiler can
 // neither forward the written values nor drop the writes.
-template <typename R> __device__ __forceinline__ void stash_put(store_t<R> *stash, int slot, const Raw12<R> &r)
+template <typename R, int NB> __device__ __forceinline__ void stash_put(store_t<R> *stash, int slot, const Raw12<R> &r)
 {
 #pragma unroll
-    for (int e = 0; e < 6; ++e) stash[(slot * 6 + e) * kBlock + threadIdx.x] = r.v[e];
+    for (int e = 0; e < 6; ++e) stash[(slot * 6 + e) * NB + threadIdx.x] = r.v[e];
 }
-template <typename R> __device__ __forceinline__ M3<R> stash_get(const store_t<R> *stash, int slot)
+template <typename R, int NB> __device__ __forceinline__ M3<R> stash_get(const store_t<R> *stash, int slot)
 {
     Raw12<R> r;
 #pragma unroll
-    for (int e = 0; e < 6; ++e) r.v[e] = stash[(slot * 6 + e) * kBlock + threadIdx.x];
+    for (int e = 0; e < 6; ++e) r.v[e] = stash[(slot * 6 + e) * NB + threadIdx.x];
     return from_raw(r);
 }
 __device__ __forceinline__ void stash_fence() { __asm__ __volatile__("" ::: "memory"); }
 
-template <int MU, typename R, bool HIT1, bool DLT, bool TWOB = false, bool MEAS = false, bool STASH = false>
+template <int MU, typename R, bool HIT1, bool DLT, bool TWOB = false, bool MEAS = false, bool STASH = false,
+          int NB = kBlock>
 __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, const Geom &g, int par, int v,
                                               double beta, uint64_t sweep, uint64_t seed, int nhit, int &att, int &acc,
                                               store_t<R> *stash, const R *wb = nullptr)
@@ -281,16 +282,16 @@ __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, co
                 e2.v[e] = pe2[e * kTile];
             }
         }
-        stash_put<R>(stash, 0, b1);
-        stash_put<R>(stash, 1, e1);
-        stash_put<R>(stash, 2, b2);
+        stash_put<R, NB>(stash, 0, b1);
+        stash_put<R, NB>(stash, 1, e1);
+        stash_put<R, NB>(stash, 2, b2);
         stash_fence();
         add_staple<MU, N0, R, DLT, TWOB>(A, from_raw(b0), from_raw(e0), links, g, x, layer, par, n, wb);
         if constexpr (MEAS && MU == 1) S = A;
-        add_staple<MU, N1, R, DLT, TWOB>(A, stash_get<R>(stash, 0), stash_get<R>(stash, 1), links, g, x, layer, par,
+        add_staple<MU, N1, R, DLT, TWOB>(A, stash_get<R, NB>(stash, 0), stash_get<R, NB>(stash, 1), links, g, x, layer, par,
                                          n, wb);
         if constexpr (MEAS && MU == 2) S = A;
-        add_staple<MU, N2, R, DLT, TWOB>(A, stash_get<R>(stash, 2), from_raw(e2), links, g, x, layer, par, n, wb);
+        add_staple<MU, N2, R, DLT, TWOB>(A, stash_get<R, NB>(stash, 2), from_raw(e2), links, g, x, layer, par, n, wb);
     }
     store_t<R> *own = planes<R>(links, g, MU, par);
     M3<R> U = load_link12_nt<R>(own, n);
@@ -306,18 +307,19 @@ __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, co
 // Exact integer heat-bath counts: packed (attempts | accepts << 16) summed
 // over the workgroup, then added to counter slot `slot`, so no two
 // concurrent workgroups update the same address.
+template <int NB = kBlock>
 __device__ __forceinline__ void count_block(int att, int acc, unsigned long long *__restrict__ counters, int slot)
 {
     unsigned packed = (unsigned)att | ((unsigned)acc << 16);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) packed += __shfl_xor(packed, off);
-    __shared__ unsigned wsum[kBlock / 64];
+    __shared__ unsigned wsum[NB / 64];
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = packed;
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long a = 0, b = 0;
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) {
+        for (int w = 0; w < NB / 64; ++w) {
             a += wsum[w] & 0xffffu;
             b += wsum[w] >> 16;
         }
@@ -330,16 +332,16 @@ __device__ __forceinline__ void count_block(int att, int acc, unsigned long long
 }
 
 // Sum of v over the workgroup, in a fixed order (valid in thread 0).
-__device__ __forceinline__ double block_sum(double v)
+template <int NB = kBlock> __device__ __forceinline__ double block_sum(double v)
 {
-    __shared__ double wsum[kBlock / 64];
+    __shared__ double wsum[NB / 64];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0)
-        for (int w = 0; w < kBlock / 64; ++w) s += wsum[w];
+        for (int w = 0; w < NB / 64; ++w) s += wsum[w];
     return s;
 }
 
@@ -354,12 +356,13 @@ __device__ __forceinline__ int pass_tile(int par)
     return par ? (int)gridDim.x - 1 - t : t;
 }
 
-// One checkerboard pass.  MEAS (odd passes of MU = 1, 2, 3): also store, per
-// workgroup, the sum over its links of the final plaquettes of the planes
-// (nu, MU), nu < MU, that update_link returns; on a double-layered torus
-// one sum per layer of the updated site.
-template <int MU, typename R, bool HIT1, bool DLT, bool MEAS = false>
-__global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update(store_t<R> *__restrict__ links, const Geom g, const int par,
+// One checkerboard pass in workgroups of NB threads (kBlock, or kPassBlock
+// for the unmeasured passes of a single torus).  MEAS (odd passes of MU = 1,
+// 2, 3; NB = kBlock): also store, per workgroup, the sum over its links of
+// the final plaquettes of the planes (nu, MU), nu < MU, that update_link
+// returns; on a double-layered torus one sum per layer of the updated site.
+template <int MU, typename R, bool HIT1, bool DLT, bool MEAS = false, int NB = kBlock>
+__global__ __launch_bounds__(NB, kPassWaves<R>) void k_update(store_t<R> *__restrict__ links, const Geom g, const int par,
                                                    const double beta, const uint64_t sweep, const uint64_t seed,
                                                    const int nhit, unsigned long long *__restrict__ counters,
                                                    double *__restrict__ meas = nullptr)
@@ -367,30 +370,30 @@ __global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update(store_t<R> *__
     constexpr bool kStash = kStashPass<R, DLT, MU>;
     store_t<R> *st = nullptr;
     if constexpr (kStash) {
-        __shared__ store_t<R> stash[kStashSlots * 6 * kBlock];
+        __shared__ store_t<R> stash[kStashSlots * 6 * NB];
         st = stash;
     }
-    const int v = pass_tile(par) * kBlock + threadIdx.x;
+    const int v = pass_tile(par) * NB + threadIdx.x;
     int att = 0, acc = 0;
     double trw = 0.0;
     if (v < g.nlat * g.Vh)
-        trw = update_link<MU, R, HIT1, DLT, false, MEAS, kStash>(links, g, par, v, beta, sweep, seed, nhit, att, acc,
+        trw = update_link<MU, R, HIT1, DLT, false, MEAS, kStash, NB>(links, g, par, v, beta, sweep, seed, nhit, att, acc,
                                                                  st);
-    count_block(att, acc, counters, blockIdx.x % kCounterSlots);
+    count_block<NB>(att, acc, counters, blockIdx.x % kCounterSlots);
     if (MEAS) {
         __syncthreads();
         if constexpr (DLT) {
             // per layer of the updated site: meas[2 b + layer]
             const bool l1 = v >= g.Vh;
-            const double b0 = block_sum(l1 ? 0.0 : trw);
+            const double b0 = block_sum<NB>(l1 ? 0.0 : trw);
             __syncthreads();
-            const double b1 = block_sum(l1 ? trw : 0.0);
+            const double b1 = block_sum<NB>(l1 ? trw : 0.0);
             if (threadIdx.x == 0) {
                 meas[2 * blockIdx.x] = b0;
                 meas[2 * blockIdx.x + 1] = b1;
             }
         } else {
-            const double b = block_sum(trw);
+            const double b = block_sum<NB>(trw);
             if (threadIdx.x == 0) meas[blockIdx.x] = b;
         }
     }
@@ -805,6 +808,8 @@ __global__ __launch_bounds__(kBlock) void k_copy(const uint4 *__restrict__ src, 
 }
 
 inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+// workgroups of nb threads covering the nlat * Vh links of one pass
+inline unsigned pass_blocks(const Geom &g, int nb) { return (unsigned)(((long long)g.nlat * g.Vh + nb - 1) / nb); }
 
 }  // namespace
 
@@ -828,16 +833,23 @@ template <int MU, typename R>
 static void update_launch(store_t<R> *links, const Geom &g, int par, double beta, uint64_t sweep, uint64_t seed,
                           int nhit, unsigned long long *counters, hipStream_t s)
 {
-    const dim3 grid(blocks_for((long long)g.nlat * g.Vh));
     const bool dlt = g.nlat == 2;
+    // one-wave workgroups on a single torus: a workgroup's LDS stash and slot
+    // are released as soon as its one wave ends (32^4: +1.4 %, 64^4: +2 %,
+    // 16^4: +7 % over four-wave workgroups); the double-layered torus keeps
+    // four-wave workgroups (-1 % with one wave)
     if (nhit == 1 && !dlt)
-        k_update<MU, R, true, false><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters);
+        k_update<MU, R, true, false, false, kPassBlock>
+            <<<pass_blocks(g, kPassBlock), kPassBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters);
     else if (nhit == 1)
-        k_update<MU, R, true, true><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters);
+        k_update<MU, R, true, true><<<pass_blocks(g, kBlock), kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit,
+                                                                              counters);
     else if (!dlt)
-        k_update<MU, R, false, false><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters);
+        k_update<MU, R, false, false, false, kPassBlock>
+            <<<pass_blocks(g, kPassBlock), kPassBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters);
     else
-        k_update<MU, R, false, true><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters);
+        k_update<MU, R, false, true><<<pass_blocks(g, kBlock), kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit,
+                                                                               counters);
 }
 
 template <typename R>

@@ -9,6 +9,7 @@
 namespace su3hb {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 waves of 64)
+constexpr int kPassBlock = 64;       // threads per workgroup of the unmeasured single-torus passes (one wave)
 constexpr int kPlaqBlocksMax = 4096; // workgroups per layer of the plaquette reduction
 constexpr int kCounterSlots = 4096;  // heat-bath counter slots (pairs of u64: attempts, accepts)
 
