@@ -470,13 +470,13 @@ __global__ __launch_bounds__(kBlock) void k_polyakov_final(const double *__restr
 // of the batch; logical tile t (pass_tile) belongs to the job whose tile range
 // holds t; job j is at sweep index sweep0 + (step - admit_step).
 template <int MU, typename R, bool HIT1, bool DLT>
-__global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update_batch(const BatchJob *__restrict__ jobs, const int njobs,
-                                                         const long long step, const int par)
+__global__ __launch_bounds__(kPassBlock, kPassWaves<R>) void k_update_batch(const BatchJob *__restrict__ jobs, const int njobs,
+                                                             const long long step, const int par)
 {
     constexpr bool kStash = kStashBatch<R, DLT>;
     store_t<R> *st = nullptr;
     if constexpr (kStash) {
-        __shared__ store_t<R> stash[kStashSlots * 6 * kBlock];
+        __shared__ store_t<R> stash[kStashSlots * 6 * kPassBlock];
         st = stash;
     }
     // the XCD-aware, parity-reversed tile of the whole batch, as for one
@@ -497,13 +497,13 @@ __global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update_batch(const Ba
     __syncthreads();
     const BatchJob &J = jobs[sj];
     const int local = t - J.tile_begin;
-    const int v = local * kBlock + threadIdx.x;
+    const int v = local * kPassBlock + threadIdx.x;
     const uint64_t sweep = J.sweep0 + (uint64_t)(step - J.admit_step);
     int att = 0, acc = 0;
     if (v < J.g.nlat * J.g.Vh)
-        update_link<MU, R, HIT1, DLT, false, false, kStash>((store_t<R> *)J.links, J.g, par, v, J.beta, sweep, J.seed,
-                                                            J.nhit, att, acc, st);
-    count_block(att, acc, J.counters, local % kCounterSlots);
+        update_link<MU, R, HIT1, DLT, false, false, kStash, kPassBlock>((store_t<R> *)J.links, J.g, par, v, J.beta,
+                                                                        sweep, J.seed, J.nhit, att, acc, st);
+    count_block<kPassBlock>(att, acc, J.counters, local % kCounterSlots);
 }
 
 // ---------------------------------------------------------------------------
@@ -878,10 +878,10 @@ template <typename R, bool HIT1, bool DLT>
 static void batch_dispatch(const BatchJob *jobs, int njobs, int ntiles, long long step, int mu, int par, hipStream_t s)
 {
     switch (mu) {
-    case 0: k_update_batch<0, R, HIT1, DLT><<<ntiles, kBlock, 0, s>>>(jobs, njobs, step, par); break;
-    case 1: k_update_batch<1, R, HIT1, DLT><<<ntiles, kBlock, 0, s>>>(jobs, njobs, step, par); break;
-    case 2: k_update_batch<2, R, HIT1, DLT><<<ntiles, kBlock, 0, s>>>(jobs, njobs, step, par); break;
-    default: k_update_batch<3, R, HIT1, DLT><<<ntiles, kBlock, 0, s>>>(jobs, njobs, step, par); break;
+    case 0: k_update_batch<0, R, HIT1, DLT><<<ntiles, kPassBlock, 0, s>>>(jobs, njobs, step, par); break;
+    case 1: k_update_batch<1, R, HIT1, DLT><<<ntiles, kPassBlock, 0, s>>>(jobs, njobs, step, par); break;
+    case 2: k_update_batch<2, R, HIT1, DLT><<<ntiles, kPassBlock, 0, s>>>(jobs, njobs, step, par); break;
+    default: k_update_batch<3, R, HIT1, DLT><<<ntiles, kPassBlock, 0, s>>>(jobs, njobs, step, par); break;
     }
 }
 

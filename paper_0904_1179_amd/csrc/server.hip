@@ -145,7 +145,7 @@ su3_status build_tables(su3_server *s)
         for (size_t k = 0; k < per[gi].size(); ++k) {
             h[k] = per[gi][k];
             h[k].tile_begin = tiles;
-            tiles += (int)(((long long)h[k].g.nlat * h[k].g.Vh + kBlock - 1) / kBlock);
+            tiles += (int)(((long long)h[k].g.nlat * h[k].g.Vh + kPassBlock - 1) / kPassBlock);
         }
         G.d_table = (BatchJob *)s->arena + (size_t)gi * s->max_active;
         G.njobs = (int)per[gi].size();

@@ -139,14 +139,21 @@ def test_m1_plaquette_table(hb):
     _say(f"M1 worst |dP| over 32 sweeps: {worst:.3e}")
 
 
-@pytest.mark.parametrize("L,nlat", [(32, 1), (64, 1), (16, 2)])
-def test_full_size_sampled_links_after_one_sweep(hb, L, nlat):
+@pytest.mark.parametrize("L,nlat,measured", [(32, 1, False), (32, 1, True), (64, 1, False), (16, 2, False),
+                                              (16, 2, True)])
+def test_full_size_sampled_links_after_one_sweep(hb, L, nlat, measured):
+    """measured: the sweep runs as the benchmark times it (su3_sweep_measure,
+    whose passes of mu = 1, 2, 3 also return the plaquette)."""
     from cone import FirstSweepCone, sample_lids
 
-    _say(f"full-size sampled parity L={L} nlat={nlat}")
+    _say(f"full-size sampled parity L={L} nlat={nlat} measured={measured}")
     lat = hb.Lattice(L, nlat=nlat, seed=1)
     lat.start(hot=True)
-    lat.sweep(1, 5.7)
+    if measured:
+        fused = lat.sweep_measure(1, 5.7)[0]
+        assert np.abs(fused - lat.plaquette()).max() < 1e-13
+    else:
+        lat.sweep(1, 5.7)
     n_links = 4 * L ** 4 * nlat
     lids = sample_lids(n_links, 40, seed=L)
     got = lat.link_sample(lids)
