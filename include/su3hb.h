@@ -77,7 +77,8 @@ typedef struct {
  * Scratch: heat-bath counter slots (64 KiB), plaquette partial sums (at most
  * 32 KiB per layer), Polyakov partial sums (16 bytes per 256 sites of a time
  * slice, per layer) and the partial sums of the measured passes of
- * su3_sweep_measure (24 bytes per 256 links of one pass).
+ * su3_sweep_measure (24 bytes per 64 links of one pass on a single torus,
+ * 48 bytes per 256 on a double-layered torus).
  * SU3_EINVAL on invalid parameters. */
 su3_status su3_footprint(const su3_params *p, size_t *link_bytes, size_t *scratch_bytes);
 

@@ -764,22 +764,23 @@ __global__ __launch_bounds__(kBlock) void k_plaq_final(const double *__restrict_
 }
 
 // single torus: sums[0] = sums[1] = sum of the partials a[0..na), fixed order
-__global__ __launch_bounds__(kBlock) void k_sum_partials(const double *__restrict__ a, int na,
-                                                         double *__restrict__ sums)
+constexpr int kSumBlock = 1024;
+__global__ __launch_bounds__(kSumBlock) void k_sum_partials(const double *__restrict__ a, int na,
+                                                            double *__restrict__ sums)
 {
-    // thread t adds a[t], a[t + kBlock], ... in that order; the loads of
+    // thread t adds a[t], a[t + kSumBlock], ... in that order; the loads of
     // eight terms are issued together
     double s = 0.0;
     int k = threadIdx.x;
-    for (; k + 7 * kBlock < na; k += 8 * kBlock) {
+    for (; k + 7 * kSumBlock < na; k += 8 * kSumBlock) {
         double v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = a[k + j * kBlock];
+        for (int j = 0; j < 8; ++j) v[j] = a[k + j * kSumBlock];
 #pragma unroll
         for (int j = 0; j < 8; ++j) s += v[j];
     }
-    for (; k < na; k += kBlock) s += a[k];
-    const double r = block_sum(s);
+    for (; k < na; k += kSumBlock) s += a[k];
+    const double r = block_sum<kSumBlock>(s);
     if (threadIdx.x == 0) {
         sums[0] = r;
         sums[1] = r;
@@ -914,17 +915,18 @@ template <int MU, typename R>
 static void update_meas_launch(store_t<R> *links, const Geom &g, double beta, uint64_t sweep, uint64_t seed, int nhit,
                                unsigned long long *counters, double *meas, hipStream_t s)
 {
+    // workgroups of meas_block_size(g) threads, as the unmeasured passes
     const dim3 grid(meas_blocks(g));
     const bool dlt = g.nlat == 2;
     if (nhit == 1 && !dlt)
-        k_update<MU, R, true, false, true><<<grid, kBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit, counters,
-                                                                    meas);
+        k_update<MU, R, true, false, true, kPassBlock><<<grid, kPassBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit,
+                                                                                  counters, meas);
     else if (nhit == 1)
         k_update<MU, R, true, true, true><<<grid, kBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit, counters,
                                                                    meas);
     else if (!dlt)
-        k_update<MU, R, false, false, true><<<grid, kBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit, counters,
-                                                                     meas);
+        k_update<MU, R, false, false, true, kPassBlock><<<grid, kPassBlock, 0, s>>>(links, g, 1, beta, sweep, seed,
+                                                                                   nhit, counters, meas);
     else
         k_update<MU, R, false, true, true><<<grid, kBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit, counters,
                                                                     meas);
@@ -941,7 +943,8 @@ static void update_meas_dispatch(store_t<R> *links, const Geom &g, int mu, doubl
     }
 }
 
-int meas_blocks(const Geom &g) { return (int)blocks_for((long long)g.nlat * g.Vh); }
+int meas_block_size(const Geom &g) { return g.nlat == 1 ? kPassBlock : kBlock; }
+int meas_blocks(const Geom &g) { return (int)pass_blocks(g, meas_block_size(g)); }
 
 int face_blocks(const Geom &g)
 {
@@ -973,7 +976,7 @@ hipError_t launch_update_measured(int precision, void *links, const Geom &g, int
 hipError_t launch_measure_final(const double *meas, const double *faces, const Geom &g, double *sums, hipStream_t s)
 {
     if (g.nlat == 1)
-        k_sum_partials<<<1, kBlock, 0, s>>>(meas, 3 * meas_blocks(g), sums);
+        k_sum_partials<<<1, kSumBlock, 0, s>>>(meas, 3 * meas_blocks(g), sums);
     else
         k_measure_final_dlt<<<1, kBlock, 0, s>>>(meas, 3 * meas_blocks(g), faces, 4 * face_blocks(g), sums);
     return hipGetLastError();
