@@ -80,14 +80,16 @@ su3_status check_params(const su3_params *p)
 // XCDs, each from HBM, so the choice takes the fewest rim links, the sum of
 // 1/w over the directions that are cut, among the widths that
 //  * give every XCD whole domains: nd * nlat a multiple of 8, nd = (L1/w1)(L2/w2);
-//  * keep one x3 slab of a domain within 16 workgroups (L0/2 w1 w2 <= 4096
-//    updates), so that the links around it are re-read while still in L2;
+//  * keep one x3 slab of a domain within kSlabMax = 4096 updates
+//    (L0/2 w1 w2 <= 4096), so that the links around it are re-read while
+//    still in L2;
 //  * keep the lanes of a wave on whole 16-link tiles: L0/2 w1 a multiple of 16,
 //    or w1 = L1.
 // Ties go to the wider w1 (longer runs of consecutive links).  Without such
 // widths the rule keeps w1 = L1 and the largest w2 <= L2/8.
 void pick_domains(const int32_t L[4], int nlat, int &w1, int &w2)
 {
+    constexpr long long kSlabMax = 4096;
     const int l0h = L[0] / 2;
     double best = 1e30;
     w1 = L[1];
@@ -97,7 +99,7 @@ void pick_domains(const int32_t L[4], int nlat, int &w1, int &w2)
         for (int b = L[2]; b >= 1; --b) {
             if (L[2] % b) continue;
             const long long nd = (long long)(L[1] / a) * (L[2] / b) * nlat;
-            if (nd % 8 || (long long)l0h * a * b > 16 * kBlock) continue;
+            if (nd % 8 || (long long)l0h * a * b > kSlabMax) continue;
             const double rim = (a < L[1] ? 1.0 / a : 0.0) + (b < L[2] ? 1.0 / b : 0.0);
             if (rim < best - 1e-12) {
                 best = rim;

@@ -1,14 +1,16 @@
 // kernels.hip -- gfx950 kernels of the checkerboard SU(3) heat bath.
 //
 // Link storage: the links of one (direction, parity) form a block of tiles of
-// 16 consecutive links, each tile holding the 9 complex entries entry-major
-// (double2 or float2); see link_at.  The link U_dir(x) of site
+// 16 consecutive links, each tile holding the 6 complex entries of rows 0 and 1
+// entry-major (double2 or float2; row 2 is rebuilt by every reader); see
+// link_at.  The link U_dir(x) of site
 // x = (layer, parity, i) is element n = layer * Vh + i of block (dir, parity).
 // Sixteen lanes with consecutive n read 16 consecutive complex numbers per
 // entry: whole 128-byte lines, fully coalesced vector loads.
 //
 // The hot kernel is k_update<MU, R>: one checkerboard pass, i.e. every link
-// U_MU(x) with parity(x) = par, one thread per link.  It gathers the 18
+// U_MU(x) with parity(x) = par, one thread per link (one-wave workgroups on a
+// single torus, four-wave ones on a double-layered torus).  It gathers the 18
 // neighbour links of the six staples (Wilson action), runs the
 // Cabibbo-Marinari heat bath on the SU(2) subgroups (0,1), (1,2), (0,2) with
 // Kennedy-Pendleton sampling, reunitarises in FP64 and writes the link back.
