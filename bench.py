@@ -41,7 +41,10 @@ READ_REALS, WRITE_REALS, READS_PER_UPDATE = 12, 12, 8
 def bytes_per_update(precision):
     return (READS_PER_UPDATE * READ_REALS + WRITE_REALS) * REAL_BYTES[precision]
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_0904_1179_amd", "csrc", f) for f in ("kernels.hip", "device.h")]
+# what the pass kernel's counters depend on: its code, its launch shape and the
+# pass order the host picks
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0904_1179_amd", "csrc", f)
+                  for f in ("kernels.hip", "device.h", "launch.h", "api.hip")]
 
 
 def kernel_source_hash():
