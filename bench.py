@@ -287,6 +287,9 @@ def main():
                 "launches_timed": main_run["passes"]}
     if not args.no_copy_probe:
         roofline["copy_probe_gbs"] = round(copy_probe_gbs(), 1)
+        # the pass's HBM traffic rate against what a plain copy reaches
+        if traffic is not None:
+            roofline["traffic_gbs_over_copy_probe"] = round(traffic / pass_s / 1e9 / roofline["copy_probe_gbs"], 3)
     spread = repeat_rates(main_run["lattice"], beta)
     del main_run["lattice"]
 
