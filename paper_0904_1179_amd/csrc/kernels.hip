@@ -301,7 +301,13 @@ __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, co
     // with per-layer couplings the staple carries them: alpha = 2k/3
     __builtin_amdgcn_s_setprio(0);
     double trw = heatbath<R, HIT1>(U, A, TWOB ? 1.0 : beta, seed, 4 * site + MU, sweep, nhit, att, acc);
-    store_link_nt<R>(own, n, U);
+    // FP64: nontemporal, so the written link does not displace staple links
+    // from L2 (a plain store: -3 % at 32^4).  FP32, bound by issue rather
+    // than memory: a plain store (+1 %)
+    if constexpr (sizeof(R) == 8)
+        store_link_nt<R>(own, n, U);
+    else
+        store_link<R>(own, n, U);
     if constexpr (MEAS && MU < 3) trw = retr_mul(U, S);
     return trw;
 }
