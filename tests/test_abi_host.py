@@ -89,3 +89,21 @@ def test_null_context_rejected(hb):
         assert getattr(lib, name)(*args) == -1
     assert lib.su3_destroy(None) == 0
     assert lib.su3_strerror(-4) == b"call out of order"
+
+
+@pytest.mark.parametrize("lang,std", [("c", "-std=c99"), ("c++", "-std=c++11")])
+def test_header_is_plain_c_and_cpp(tmp_path, lang, std):
+    """include/su3hb.h declares a C ABI: it must compile as strict C99 (and as
+    C++), with nothing but plain types in the signatures."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc" if lang == "c" else "g++")
+    if cc is None:
+        pytest.skip("no host compiler")
+    src = tmp_path / "use_header.c"
+    src.write_text('#include "su3hb.h"\nint main(void) { su3_params p; (void)p; return 0; }\n')
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    r = subprocess.run([cc, std, "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only", "-x", lang, "-I", inc,
+                        str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
