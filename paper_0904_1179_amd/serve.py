@@ -1,10 +1,11 @@
 """Serving loop: continuous batching of lattice jobs on one GPU.
 
-Thin binding of the su3_server_* entry points of the C ABI plus the driver
+Thin binding of the su3_server_* entry points of the C ABI plus the loop
 that feeds a timed job stream into the server.  The server (native, in the
-library) admits jobs by HBM footprint inside one caller-owned arena, runs one
-batched sweep of every admitted job per step and retires finished jobs; the
-driver only submits arrivals, steps and records times.
+library) admits jobs by HBM footprint inside one caller-owned arena, runs
+batched sweeps of every admitted job (one per su3_server_step, up to a given
+number per su3_server_run) and retires finished jobs; the feeding loop only
+submits arrivals, runs the server and records times.
 """
 import ctypes as C
 import time
