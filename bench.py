@@ -161,16 +161,18 @@ def fp32_deviation(L, beta, sweeps=2, seed=1):
     return out
 
 
-def config_rate(L, nlat, precision, beta, sweeps, seed=1, flip_mask=None):
+def config_rate(L, nlat, precision, beta, sweeps, seed=1, flip_mask=None, hot=True, untimed=1):
     """Link updates/s of `sweeps` sweeps (each with its plaquette) on one more
-    workload configuration, hot start excluded; also the last plaquettes."""
+    workload configuration, after the start and `untimed` untimed sweeps; also
+    the algorithmic bytes per second of the passes and the last plaquettes."""
     import torch
 
     from paper_0904_1179_amd import Lattice
 
     lat = Lattice(L, nlat=nlat, precision=precision, seed=seed, flip_mask=flip_mask)
-    lat.start(hot=True)
-    lat.sweep(1, beta)
+    lat.start(hot=hot)
+    if untimed:
+        lat.sweep(untimed, beta)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plaq = lat.sweep_measure(sweeps, beta)
@@ -180,6 +182,7 @@ def config_rate(L, nlat, precision, beta, sweeps, seed=1, flip_mask=None):
     del lat
     torch.cuda.empty_cache()
     return {"value": updates / t, "unit": "link updates/s", "sweeps": sweeps, "seconds": t,
+            "algorithmic_gbs": round(updates / t * bytes_per_update(precision) / 1e9, 1),
             "plaquette_last": [float(x) for x in plaq[-1]]}
 
 
@@ -319,10 +322,15 @@ def main():
                        "note": "FP32 links and products; FP64 heat-bath scalars, reunitarisation and sums"}
 
     if not args.no_configs and prec == 64:
-        # the other timed workload configurations: a double-layered 2 x 16^4 torus (flip mask 0x7) at beta 5.7,
-        # 64^4 at beta 6.0 in both precisions (10 sweeps each after one untimed sweep), and the double-layered
-        # torus with per-layer couplings 5.5 / 6.2 (32 sweeps) with its Polyakov loops
+        # the other timed workload configurations: 8^4 from a cold start, 32 sweeps (launch-bound: reported
+        # only); 16^4 in both precisions (the lattice fits in the 256 MB Infinity Cache: not an HBM figure);
+        # a double-layered 2 x 16^4 torus (flip mask 0x7) at beta 5.7; 64^4 at beta 6.0 in both precisions
+        # (10 sweeps each after one untimed sweep); the double-layered torus with per-layer couplings
+        # 5.5 / 6.2 (32 sweeps) with its Polyakov loops
         out["configs"] = {
+            "8^4_fp64_cold_beta5.7": config_rate(8, 1, 64, 5.7, 32, hot=False, untimed=0),
+            "16^4_fp64_beta5.7": config_rate(16, 1, 64, 5.7, 32),
+            "16^4_fp32_beta5.7": config_rate(16, 1, 32, 5.7, 32),
             "dlt_2x16^4_fp64_beta5.7": config_rate(16, 2, 64, 5.7, 32, flip_mask=0x7),
             "64^4_fp64_beta6.0": config_rate(64, 1, 64, 6.0, 10),
             "64^4_fp32_beta6.0": config_rate(64, 1, 32, 6.0, 10),
