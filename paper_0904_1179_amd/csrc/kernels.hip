@@ -620,7 +620,46 @@ __device__ __forceinline__ double plaq_plane(const store_t<R> *__restrict__ link
     return s;
 }
 
+// Rows 0 and 1 of a link (row 2 never formed), in FP64.
+template <typename R> __device__ __forceinline__ M3<double> load_rows01(const store_t<R> *block, int n)
+{
+    M3<double> m;
+    const store_t<R> *p = link_at<R>(block, n);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        const store_t<R> v = p[e * kTile];
+        m.e[e / 3][e % 3] = Cx<double>{(double)v.x, (double)v.y};
+    }
+    return m;
+}
+
+// Plane (MU, NU) of a site whose own links U (rows 0, 1) are already held:
+// Re Tr P Q^+ with P = U_MU(x) U_NU(x+MU), Q = U_NU(x) U_MU(x+NU), both
+// SU(3) products formed as rows 0, 1 with row 2 rebuilt.
+template <int MU, int NU, typename R, bool DLT>
+__device__ __forceinline__ double plaq_plane_own(const store_t<R> *__restrict__ links, const Geom &g, const int x[4],
+                                                 int layer, int par, const M3<double> *U)
+{
+    const int opp = par ^ 1;
+    const M3<double> P = mul_nn_su3(
+        U[MU], convert<double>(load_link12<R>(planes<R>(links, g, NU, opp), nbr_elem<MU, +1, NU, 0, DLT>(g, x, layer))));
+    const M3<double> Q = mul_nn_su3(
+        U[NU], convert<double>(load_link12<R>(planes<R>(links, g, MU, opp), nbr_elem<NU, +1, MU, 0, DLT>(g, x, layer))));
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) s += P.e[a][b].re * Q.e[a][b].re + P.e[a][b].im * Q.e[a][b].im;
+    return s;
+}
+
 // The six planes of the site.
+//  * FP64: every plane loads its four links; the compiler issues the loads of
+//    both sites of a thread at once (one wave per SIMD).
+//  * FP32: the four own links are loaded once and kept, and compiler-only
+//    fences between the planes hold the neighbour loads back (two waves per
+//    SIMD: 87 instead of 122 us at 32^4).  In FP64 the same scheme took the
+//    same time with 31 % more bytes fetched.
 template <typename R, bool DLT>
 __device__ __forceinline__ double plaq_site(const store_t<R> *__restrict__ links, const Geom &g, int layer, int par,
                                            int i)
@@ -628,13 +667,32 @@ __device__ __forceinline__ double plaq_site(const store_t<R> *__restrict__ links
     int x[4];
     site_coords(g, par, i, x);
     const int n = layer * g.Vh + i;
-    double s = plaq_plane<0, 1, R, DLT>(links, g, x, layer, par, n);
-    s += plaq_plane<0, 2, R, DLT>(links, g, x, layer, par, n);
-    s += plaq_plane<1, 2, R, DLT>(links, g, x, layer, par, n);
-    s += plaq_plane<0, 3, R, DLT>(links, g, x, layer, par, n);
-    s += plaq_plane<1, 3, R, DLT>(links, g, x, layer, par, n);
-    s += plaq_plane<2, 3, R, DLT>(links, g, x, layer, par, n);
-    return s;
+    if constexpr (sizeof(R) == 8) {
+        double s = plaq_plane<0, 1, R, DLT>(links, g, x, layer, par, n);
+        s += plaq_plane<0, 2, R, DLT>(links, g, x, layer, par, n);
+        s += plaq_plane<1, 2, R, DLT>(links, g, x, layer, par, n);
+        s += plaq_plane<0, 3, R, DLT>(links, g, x, layer, par, n);
+        s += plaq_plane<1, 3, R, DLT>(links, g, x, layer, par, n);
+        s += plaq_plane<2, 3, R, DLT>(links, g, x, layer, par, n);
+        return s;
+    } else {
+        M3<double> U[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) U[mu] = load_rows01<R>(planes<R>(links, g, mu, par), n);
+        double s = plaq_plane_own<0, 1, R, DLT>(links, g, x, layer, par, U);
+        stash_fence();
+        s += plaq_plane_own<0, 2, R, DLT>(links, g, x, layer, par, U);
+        stash_fence();
+        s += plaq_plane_own<1, 2, R, DLT>(links, g, x, layer, par, U);
+        stash_fence();
+        s += plaq_plane_own<0, 3, R, DLT>(links, g, x, layer, par, U);
+        stash_fence();
+        s += plaq_plane_own<1, 3, R, DLT>(links, g, x, layer, par, U);
+        stash_fence();
+        s += plaq_plane_own<2, 3, R, DLT>(links, g, x, layer, par, U);
+        stash_fence();
+        return s;
+    }
 }
 
 // Grid (nblk, nlat).  Workgroup b (XCD-remapped) sums the contiguous run of
