@@ -21,8 +21,9 @@ COMPILE = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
            "-I" + os.path.join(ROOT, "include")]
 
 
-def _run(cmd):
-    res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+def _run(cmd, tmpdir=None):
+    env = dict(os.environ, TMPDIR=tmpdir) if tmpdir else None
+    res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, env=env)
     out = "\n".join(l for l in res.stdout.splitlines() if "packed-fp32-ops" not in l)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + out)
@@ -30,12 +31,17 @@ def _run(cmd):
 
 
 def build() -> str:
-    with tempfile.TemporaryDirectory(prefix="su3hb_build_") as tmp:
+    # object files in a scratch folder inside the package (removed afterwards;
+    # `_build/` is git-ignored)
+    scratch = os.path.join(HERE, "_build")
+    os.makedirs(scratch, exist_ok=True)
+    with tempfile.TemporaryDirectory(prefix="su3hb_", dir=scratch) as tmp:
         objs = [os.path.join(tmp, os.path.basename(s) + ".o") for s in SOURCES]
         with ThreadPoolExecutor(max_workers=len(SOURCES)) as pool:
-            list(pool.map(_run, [[HIPCC] + COMPILE + ["-c", src, "-o", obj] for src, obj in zip(SOURCES, objs)]))
+            list(pool.map(lambda c: _run(c, tmp),
+                          [[HIPCC] + COMPILE + ["-c", src, "-o", obj] for src, obj in zip(SOURCES, objs)]))
         out = LIB + ".tmp"
-        _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out] + objs)
+        _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out] + objs, tmp)
         os.replace(out, LIB)
     return LIB
 
