@@ -161,10 +161,12 @@ def fp32_deviation(L, beta, sweeps=2, seed=1):
     return out
 
 
-def config_rate(L, nlat, precision, beta, sweeps, seed=1, flip_mask=None, hot=True, untimed=1):
-    """Link updates/s of `sweeps` sweeps (each with its plaquette) on one more
-    workload configuration, after the start and `untimed` untimed sweeps; also
-    the algorithmic bytes per second of the passes and the last plaquettes."""
+def config_rate(L, nlat, precision, beta, sweeps, seed=1, flip_mask=None, hot=True, untimed=1, every=True):
+    """Link updates/s of `sweeps` sweeps on one more workload configuration,
+    after the start and `untimed` untimed sweeps, with the plaquette after
+    every sweep (every=True) or once after the last (outside the timed
+    region); also the algorithmic bytes per second of the passes and the last
+    plaquettes."""
     import torch
 
     from paper_0904_1179_amd import Lattice
@@ -175,9 +177,14 @@ def config_rate(L, nlat, precision, beta, sweeps, seed=1, flip_mask=None, hot=Tr
         lat.sweep(untimed, beta)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plaq = lat.sweep_measure(sweeps, beta)
+    if every:
+        plaq = lat.sweep_measure(sweeps, beta)
+    else:
+        lat.sweep(sweeps, beta)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    if not every:
+        plaq = [lat.plaquette()]
     updates = 4 * lat.V * nlat * sweeps
     del lat
     torch.cuda.empty_cache()
@@ -324,7 +331,8 @@ def main():
     if not args.no_configs and prec == 64:
         # the other timed workload configurations: 8^4 from a cold start, 32 sweeps (launch-bound: reported
         # only); 16^4 in both precisions (the lattice fits in the 256 MB Infinity Cache: not an HBM figure);
-        # a double-layered 2 x 16^4 torus (flip mask 0x7) at beta 5.7; 64^4 at beta 6.0 in both precisions
+        # a double-layered 2 x 16^4 torus (flip mask 0x7) at beta 5.7, with the per-layer plaquette after every
+        # sweep and, separately, only after the last; 64^4 at beta 6.0 in both precisions
         # (10 sweeps each after one untimed sweep); the double-layered torus with per-layer couplings
         # 5.5 / 6.2 (32 sweeps) with its Polyakov loops
         out["configs"] = {
@@ -332,6 +340,7 @@ def main():
             "16^4_fp64_beta5.7": config_rate(16, 1, 64, 5.7, 32),
             "16^4_fp32_beta5.7": config_rate(16, 1, 32, 5.7, 32),
             "dlt_2x16^4_fp64_beta5.7": config_rate(16, 2, 64, 5.7, 32, flip_mask=0x7),
+            "dlt_2x16^4_fp64_beta5.7_plaquette_at_end": config_rate(16, 2, 64, 5.7, 32, flip_mask=0x7, every=False),
             "64^4_fp64_beta6.0": config_rate(64, 1, 64, 6.0, 10),
             "64^4_fp32_beta6.0": config_rate(64, 1, 32, 6.0, 10),
             "dlt_2x16^4_fp64_beta5.5|6.2": two_coupling_rate(16, 5.5, 6.2, 32)}
