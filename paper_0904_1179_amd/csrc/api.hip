@@ -155,7 +155,7 @@ size_t faces_offset(const Geom &g)
 
 size_t polyakov_offset(const Geom &g)
 {
-    const long long faces = g.nlat == 2 ? 2 * 4 * 8LL * face_blocks(g) : 0;
+    const long long faces = g.nlat == 2 ? 2 * su3hb::kFaceGroups * 8LL * face_blocks(g) : 0;
     return (size_t)round_up((long long)faces_offset(g) + faces, 256);
 }
 

@@ -43,13 +43,14 @@ hipError_t launch_plaquette(int precision, const void *links, const Geom &g, dou
 // torus, meas[2 b + layer of the updated site] on a double-layered torus, b <
 // meas_blocks(g) (workgroups of meas_block_size(g) threads: one wave on a
 // single torus, four on a double-layered one).  The three passes write
-// consecutive slices of
-// nlat * meas_blocks(g) doubles.  On a double-layered torus launch_plaq_faces
-// then sums the plaquettes those passes file under the wrong layer
-// (2 * 4 * face_blocks(g) doubles).  launch_measure_final adds everything up
-// into sums[0] (total) and sums[1 + l] (layer l).
+// consecutive slices of nlat * meas_blocks(g) doubles.  On a double-layered
+// torus launch_plaq_faces then sums the plaquettes those passes file under
+// the wrong layer (2 * kFaceGroups * face_blocks(g) doubles, one group per
+// plane (nu, mu)).  launch_measure_final adds everything up into sums[0]
+// (total) and sums[1 + l] (layer l).
 int meas_block_size(const Geom &g);
 int meas_blocks(const Geom &g);
+constexpr int kFaceGroups = 6;
 int face_blocks(const Geom &g);
 hipError_t launch_update_measured(int precision, void *links, const Geom &g, int mu, double beta, uint64_t sweep,
                                   uint64_t seed, int nhit, unsigned long long *counters, double *meas, hipStream_t s);
