@@ -325,7 +325,8 @@ def test_sweep_measure_against_oracle(hb, precision):
     assert np.all(np.abs(got[:, 0] - ref) <= 2e-3)
 
 
-@pytest.mark.parametrize("L,flip", [((4, 4, 4, 6), 0x7), ((4, 6, 4, 4), 0xF)])
+@pytest.mark.parametrize("L,flip", [((4, 4, 4, 6), 0x7), ((4, 6, 4, 4), 0xF), ((6, 4, 4, 4), 0x5), ((4, 4, 6, 2), 0x2),
+                                    ((4, 4, 4, 4), 0x8)])
 def test_dlt_sweep_measure_per_layer_against_oracle(hb, L, flip):
     """The fused measurement of a double-layered torus (passes + boundary
     plaquettes moved to their base site's layer) against the oracle's per-layer
