@@ -257,19 +257,19 @@ def cpu_baseline(L, beta, seed=1, min_seconds=1.5, max_sweeps=64):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--gpus", type=int, default=1, help="must be 1: one lattice on one GPU")
+    ap.add_argument("--steps", type=int, default=50, help="timed steps (sweep + fused plaquette)")
     # the first ~60 sweeps of a process run up to 15% slower while the GPU warms
     # up (a second lattice in the same process runs at full speed at once)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--L", type=int, default=32)
+    ap.add_argument("--warmup", type=int, default=100, help="untimed steps before the timed region")
+    ap.add_argument("--L", type=int, default=32, help="extent of the L^4 periodic lattice")
     ap.add_argument("--beta", type=float, default=5.7)
     ap.add_argument("--precision", type=int, default=64, choices=(64, 32))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--no-copy-probe", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-link run")
+    ap.add_argument("--no-copy-probe", action="store_true", help="skip the 1 GiB copy bandwidth probe")
     ap.add_argument("--no-serving", action="store_true", help="skip the mixed job stream")
-    ap.add_argument("--no-configs", action="store_true", help="skip the 2x16^4 DLT and 64^4 configurations")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other configurations (8^4, 16^4, 2x16^4 DLT, 64^4)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
