@@ -33,13 +33,24 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 REAL_BYTES = {64: 8, 32: 4}
 # Algorithmic bytes of one link update in a pass: the pass reads every link of
-# the lattice once (8 reads per updated link) and writes the updated link.
-# A link is stored and moved as its rows 0 and 1 (12 reals; row 2 is rebuilt).
-READ_REALS, WRITE_REALS, READS_PER_UPDATE = 12, 12, 8
+# the lattice once (8 link reads per updated link) and writes the updated
+# link, 9 link transfers of an SU(3) matrix of 18 reals (the paper's storage).
+# The roofline fraction is taken against this figure.  This library stores a
+# link as its rows 0 and 1 (12 reals, row 2 rebuilt), so the bytes it must
+# move are 9 x 12 reals; that figure is reported beside it as "stored".
+LINK_REALS, STORED_REALS, TRANSFERS_PER_UPDATE = 18, 12, 9
 
 
 def bytes_per_update(precision):
-    return (READS_PER_UPDATE * READ_REALS + WRITE_REALS) * REAL_BYTES[precision]
+    """Algorithmic bytes per link update: 9 transfers of an 18-real link."""
+    return TRANSFERS_PER_UPDATE * LINK_REALS * REAL_BYTES[precision]
+
+
+def stored_bytes_per_update(precision):
+    """Bytes per link update with 12-real storage: 9 transfers of rows 0 and 1."""
+    return TRANSFERS_PER_UPDATE * STORED_REALS * REAL_BYTES[precision]
+
+
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 # what the pass kernel's counters depend on: its code, its launch shape and the
 # pass order the host picks
@@ -161,12 +172,29 @@ def fp32_deviation(L, beta, sweeps=2, seed=1):
     return out
 
 
+def chain_deviation(p32, p64, bound=1e-5):
+    """Per-sweep plaquette relative error of an FP32 chain against the FP64
+    chain from the same start: the values, their maximum before the first
+    sweep above `bound` (the onset of decorrelation, after which the two
+    chains are independent samples) and that onset (1-based; null if none)."""
+    import numpy as np
+
+    p32, p64 = np.asarray(p32, dtype=float), np.asarray(p64, dtype=float)
+    rel = np.abs(p32 - p64) / np.abs(p64)
+    over = np.nonzero(rel > bound)[0]
+    onset = int(over[0]) if over.size else None
+    before = rel[:onset] if onset is not None else rel
+    return {"rel_err_per_sweep": [float(f"{x:.3e}") for x in rel],
+            "max_rel_err_before_onset": float(before.max()) if before.size else None,
+            "onset_sweep": None if onset is None else onset + 1, "bound": bound}
+
+
 def config_rate(L, nlat, precision, beta, sweeps, seed=1, flip_mask=None, hot=True, untimed=1, every=True):
     """Link updates/s of `sweeps` sweeps on one more workload configuration,
     after the start and `untimed` untimed sweeps, with the plaquette after
     every sweep (every=True) or once after the last (outside the timed
-    region); also the algorithmic bytes per second of the passes and the last
-    plaquettes."""
+    region); also the algorithmic bytes per second of the passes and the
+    plaquettes (all sweeps with every=True, kept for the FP32 comparison)."""
     import torch
 
     from paper_0904_1179_amd import Lattice
@@ -190,7 +218,9 @@ def config_rate(L, nlat, precision, beta, sweeps, seed=1, flip_mask=None, hot=Tr
     torch.cuda.empty_cache()
     return {"value": updates / t, "unit": "link updates/s", "sweeps": sweeps, "seconds": t,
             "algorithmic_gbs": round(updates / t * bytes_per_update(precision) / 1e9, 1),
-            "plaquette_last": [float(x) for x in plaq[-1]]}
+            "stored_gbs": round(updates / t * stored_bytes_per_update(precision) / 1e9, 1),
+            "plaquette_last": [float(x) for x in plaq[-1]],
+            "_plaquette_series": [float(x[0]) for x in plaq]}
 
 
 def two_coupling_rate(L, beta0, beta1, sweeps, seed=1):
@@ -218,58 +248,217 @@ def two_coupling_rate(L, beta0, beta1, sweeps, seed=1):
     return out
 
 
-def cpu_baseline(L, beta, seed=1, min_seconds=1.5, max_sweeps=64):
-    """The FP64 oracle, as it stands, on the host cores: sweeps of the same
-    lattice, one at a time, until min_seconds of wall time have passed."""
+def host_cpu():
+    """Host CPU model (lscpu, else /proc/cpuinfo), core counts and the OpenMP thread count."""
+    import subprocess
+
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            model = "unknown"
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or nproc
+    return {"model": model, "nproc": nproc, "cpu_count": os.cpu_count(), "omp_threads": threads}
+
+
+def oracle_rate(L, nlat, beta, sweeps, threads, hot=True, flip_mask=None, seed=1, min_seconds=None):
+    """The FP64 oracle on the host: `sweeps` sweeps (or, with min_seconds,
+    sweeps one at a time until that much wall time has passed) after the
+    start, which is excluded from the time as the paper excludes it."""
     from oracle import su3ref
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    lat = su3ref.Oracle(L, nlat=1, seed=seed)
-    lat.start(True)
-    sweeps = 0
+    lat = su3ref.Oracle(L, nlat=nlat, flip_mask=flip_mask, seed=seed)
+    lat.start(hot)
+    done = 0
     t0 = time.perf_counter()
-    while sweeps < max_sweeps:
-        lat.sweep(1, beta, nthreads=threads)
-        sweeps += 1
-        if time.perf_counter() - t0 >= min_seconds:
-            break
-    t = time.perf_counter() - t0
-    one = su3ref.Oracle(16, nlat=1, seed=seed)
-    one.start(True)
-    t1 = time.perf_counter()
-    one.sweep(1, beta, nthreads=1)
-    t_one = time.perf_counter() - t1
-    cpu = "unknown"
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                cpu = line.split(":", 1)[1].strip()
+    if min_seconds is None:
+        lat.sweep(sweeps, beta, nthreads=threads)
+        done = sweeps
+    else:
+        while done < sweeps:
+            lat.sweep(1, beta, nthreads=threads)
+            done += 1
+            if time.perf_counter() - t0 >= min_seconds:
                 break
-    except OSError:
-        pass
-    return {"value": sweeps * 4 * L ** 4 / t, "unit": "link updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{sweeps} sweeps of the {L}^4 hot-start lattice ({sweeps * 4 * L ** 4} link updates) at "
-                      f"beta={beta}, OpenMP over the links of each pass; start excluded",
-            "seconds": t, "cpu_seconds_approx": t * threads, "host_cpu": cpu,
-            "single_core": {"value": 4 * 16 ** 4 / t_one, "us_per_update": t_one / (4 * 16 ** 4) * 1e6,
-                            "sample": "1 sweep of a 16^4 hot-start lattice, 1 thread"}}
+    t = time.perf_counter() - t0
+    V = (L ** 4) if isinstance(L, int) else int(__import__("numpy").prod(L))
+    ups = 4 * V * nlat * done
+    return {"value": ups / t, "unit": "link updates/s", "threads": threads, "sweeps": done, "seconds": round(t, 3),
+            "us_per_update_core": t * threads / ups * 1e6, "plaquette_last": [float(x) for x in lat.plaquette()]}
+
+
+def cpu_baseline(L, beta, seed=1, min_seconds=1.5, max_sweeps=64, configs=True):
+    """The FP64 oracle, as it stands, on the host cores: the headline lattice
+    (sweeps one at a time until min_seconds of wall time have passed, all
+    cores) and, with configs, the other workload configurations: 8^4 cold 32
+    sweeps (all cores and one core), the 2 x 16^4 double-layered torus 32
+    sweeps and 64^4 at beta 6.0 10 sweeps (all cores)."""
+    cpu = host_cpu()
+    threads = cpu["omp_threads"]
+    head = oracle_rate(L, 1, beta, max_sweeps, threads, seed=seed, min_seconds=min_seconds)
+    one = oracle_rate(16, 1, beta, 1, 1, seed=seed)
+    out = {"value": head["value"], "unit": "link updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"{head['sweeps']} sweeps of the {L}^4 hot-start lattice ({head['sweeps'] * 4 * L ** 4} link "
+                     f"updates) at beta={beta}, OpenMP over the links of each pass; start excluded",
+           "seconds": head["seconds"], "cpu_seconds_approx": head["seconds"] * threads,
+           "host_cpu": cpu["model"], "nproc": cpu["nproc"], "cpu_count": cpu["cpu_count"],
+           "single_core": {"value": one["value"], "us_per_update": one["us_per_update_core"],
+                           "sample": "1 sweep of a 16^4 hot-start lattice, 1 thread"}}
+    if configs:
+        out["configs"] = {
+            "8^4_fp64_cold_beta5.7_32sweeps": oracle_rate(8, 1, 5.7, 32, threads, hot=False, seed=seed),
+            "8^4_fp64_cold_beta5.7_32sweeps_1core": oracle_rate(8, 1, 5.7, 32, 1, hot=False, seed=seed),
+            "dlt_2x16^4_fp64_beta5.7_32sweeps": oracle_rate(16, 2, 5.7, 32, threads, flip_mask=0x7, seed=seed),
+            "64^4_fp64_beta6.0_10sweeps": oracle_rate(64, 1, 6.0, 10, threads, seed=seed)}
+    return out
+
+
+def served_fp32_deviation(jobs, recs, count=8):
+    """FP32 error of served jobs: for `count` jobs of the stream, the final
+    plaquette of the served FP32 chain against the same job run alone in
+    FP64 (same seed, start, beta and sweeps).  The jobs run 50-500 sweeps, past
+    the onset of decorrelation of FP32 and FP64 chains (an accept/reject
+    decision taken differently), so the deviation is a thermal fluctuation of
+    order (6 V)^-1/2, reported with that scale."""
+    import numpy as np
+
+    from paper_0904_1179_amd import Lattice
+
+    out = []
+    for j in sorted(jobs, key=lambda j: j["id"])[:count]:
+        lat = Lattice(j["L"], precision=64, seed=j["seed"])
+        lat.start(j.get("hot", 1))
+        lat.sweep(j["nsweeps"], j["beta"])
+        p64 = float(lat.plaquette()[0])
+        p32 = float(recs[j["id"]]["plaquette"][0])
+        V = j["L"] ** 4
+        out.append({"job": j["id"], "L": j["L"], "sweeps": j["nsweeps"], "fp32": p32, "fp64": p64,
+                    "rel_err": abs(p32 - p64) / abs(p64), "fluctuation_scale": float((6 * V) ** -0.5)})
+        del lat
+    return {"jobs": out, "max_rel_err": max(o["rel_err"] for o in out),
+            "note": "final plaquette of the served FP32 job vs the same job alone in FP64; chains this long have "
+                    "decorrelated, so compare with fluctuation_scale"}
+
+
+def startup_trace(L, beta, blocks=20, per_block=10, seed=1):
+    """Sweep time from the first sweep of the process: lattice A from a hot
+    start, `blocks` blocks of `per_block` sweeps each timed with HIP events on
+    its stream, then a second lattice B allocated and started the same way;
+    the GPU's clocks, power and temperature are sampled meanwhile (amdsmi)."""
+    import threading
+
+    import torch
+
+    from paper_0904_1179_amd import Lattice
+
+    samples, stop = [], threading.Event()
+    smi = None
+    try:
+        import amdsmi
+
+        amdsmi.amdsmi_init()
+        smi = amdsmi.amdsmi_get_processor_handles()[0]
+    except Exception as e:  # noqa: BLE001 -- the trace still runs without clock samples
+        samples.append({"error": repr(e)})
+
+    def sample():
+        import amdsmi
+
+        while not stop.is_set():
+            t = time.perf_counter()
+            try:
+                m = amdsmi.amdsmi_get_gpu_metrics_info(smi)
+                rec = {"t": t}
+                for k in ("current_gfxclk", "average_gfxclk_frequency", "current_uclk", "current_socket_power",
+                          "average_socket_power", "temperature_hotspot", "temperature_mem"):
+                    v = m.get(k)
+                    if isinstance(v, (int, float)):
+                        rec[k] = v
+                samples.append(rec)
+            except Exception as e:  # noqa: BLE001
+                samples.append({"t": t, "error": repr(e)})
+                return
+            time.sleep(0.002)
+
+    th = None
+    if smi is not None:
+        th = threading.Thread(target=sample, daemon=True)
+        th.start()
+
+    def run(lat):
+        out = []
+        for _ in range(blocks):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ta = time.perf_counter()
+            e0.record(lat.stream)
+            lat.sweep(per_block, beta)
+            e1.record(lat.stream)
+            e1.synchronize()
+            out.append((ta, time.perf_counter(), e0.elapsed_time(e1) / per_block))
+        return out
+
+    t_begin = time.perf_counter()
+    a = Lattice(L, seed=seed)
+    a.start(True)
+    torch.cuda.synchronize()
+    ra = run(a)
+    b = Lattice(L, seed=seed + 1)
+    b.start(True)
+    torch.cuda.synchronize()
+    rb = run(b)
+    stop.set()
+    if th is not None:
+        th.join()
+
+    def clocks(t0, t1):
+        sel = [s for s in samples if "t" in s and t0 <= s["t"] <= t1 and "error" not in s]
+        if not sel:
+            return {}
+        keys = set().union(*[s.keys() for s in sel]) - {"t"}
+        return {k: round(sum(s[k] for s in sel if k in s) / len([s for s in sel if k in s]), 1) for k in keys}
+
+    def rows(r):
+        return [{"ms_per_sweep": round(ms, 4), "t_s": round(ta - t_begin, 3), **clocks(ta, tb)} for ta, tb, ms in r]
+
+    return {"lattice": f"{L}^4 FP64 hot start, beta={beta}, su3_sweep in blocks of {per_block} sweeps",
+            "A_first_lattice": rows(ra), "B_second_lattice": rows(rb),
+            "samples": len([s for s in samples if "error" not in s]),
+            "sample_errors": [s["error"] for s in samples if "error" in s][:3]}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1, help="must be 1: one lattice on one GPU")
     ap.add_argument("--steps", type=int, default=50, help="timed steps (sweep + fused plaquette)")
-    # the first ~60 sweeps of a process run up to 15% slower while the GPU warms
-    # up (a second lattice in the same process runs at full speed at once)
     ap.add_argument("--warmup", type=int, default=100, help="untimed steps before the timed region")
     ap.add_argument("--L", type=int, default=32, help="extent of the L^4 periodic lattice")
     ap.add_argument("--beta", type=float, default=5.7)
     ap.add_argument("--precision", type=int, default=64, choices=(64, 32))
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
+    ap.add_argument("--no-cpu-configs", action="store_true",
+                    help="time the CPU oracle on the headline lattice only (not 8^4, 2x16^4, 64^4)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-link run")
     ap.add_argument("--no-copy-probe", action="store_true", help="skip the 1 GiB copy bandwidth probe")
     ap.add_argument("--no-serving", action="store_true", help="skip the mixed job stream")
     ap.add_argument("--no-configs", action="store_true", help="skip the other configurations (8^4, 16^4, 2x16^4 DLT, 64^4)")
+    ap.add_argument("--startup-trace", action="store_true",
+                    help="only trace the sweep time from the process's first sweep (two lattices, clocks sampled)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -282,19 +471,25 @@ def main():
 
     torch.cuda.set_device(0)
     L, beta, prec = args.L, args.beta, args.precision
+    if args.startup_trace:
+        print(json.dumps(startup_trace(L, beta)), flush=True)
+        return
     main_run = run_gpu(L, prec, args.steps, args.warmup, beta)
     ups = main_run["updates"] / main_run["seconds"]
     pass_s = main_run["pass_ms"] * 1e-3
     links_per_pass = L ** 4 // 2
     alg_bytes = bytes_per_update(prec) * links_per_pass
+    stored_bytes = stored_bytes_per_update(prec) * links_per_pass
     achieved = alg_bytes / pass_s / 1e9
     traffic = stored_traffic(f"k_update_{L}x4_fp{prec}_traffic.txt")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": f"k_update<mu, {'double' if prec == 64 else 'float'}>",
-                "algorithmic_bytes_per_launch": alg_bytes, "algorithmic_bytes_per_update": bytes_per_update(prec),
-                "updates_per_s_vs_18_real_roofline": round(links_per_pass / pass_s / (HBM_PEAK_GBS * 1e9 / (9 * 18 * REAL_BYTES[prec])), 4), "launch_us": round(main_run["pass_ms"] * 1e3, 2),
-                "launches_timed": main_run["passes"]}
+                "algorithmic_bytes_per_update": bytes_per_update(prec), "algorithmic_bytes_per_launch": alg_bytes,
+                "stored_bytes_per_update": stored_bytes_per_update(prec), "stored_bytes_per_launch": stored_bytes,
+                "achieved_stored_gbs": round(stored_bytes / pass_s / 1e9, 1),
+                "frac_stored": round(stored_bytes / pass_s / 1e9 / HBM_PEAK_GBS, 4),
+                "launch_us": round(main_run["pass_ms"] * 1e3, 2), "launches_timed": main_run["passes"]}
     if not args.no_copy_probe:
         roofline["copy_probe_gbs"] = round(copy_probe_gbs(), 1)
         # the pass's HBM traffic rate against what a plain copy reaches
@@ -321,12 +516,15 @@ def main():
         r32 = run_gpu(L, 32, args.steps, args.warmup, beta)
         del r32["lattice"]
         v32 = r32["updates"] / r32["seconds"]
-        alg32 = bytes_per_update(32) * links_per_pass
+        pass32 = r32["pass_ms"] * 1e-3
         out["fp32"] = {"value": v32, "unit": "link updates/s", "speedup_vs_fp64": v32 / ups,
                        "launch_us": round(r32["pass_ms"] * 1e3, 2),
-                       "achieved_gbs": round(alg32 / (r32["pass_ms"] * 1e-3) / 1e9, 1),
-                       "plaquette_rel_err_vs_fp64_per_sweep": fp32_deviation(L, beta),
-                       "note": "FP32 links and products; FP64 heat-bath scalars, reunitarisation and sums"}
+                       "achieved_gbs": round(bytes_per_update(32) * links_per_pass / pass32 / 1e9, 1),
+                       "achieved_stored_gbs": round(stored_bytes_per_update(32) * links_per_pass / pass32 / 1e9, 1),
+                       "plaquette_rel_err_vs_fp64_first_sweeps": fp32_deviation(L, beta),
+                       "timed_steps_vs_fp64_chain": chain_deviation(r32["plaquette"], main_run["plaquette"]),
+                       "note": "FP32 links, products and heat-bath scalars; FP64 reunitarisation and sums. Errors: "
+                               "per-sweep plaquette of the FP32 chain against the FP64 chain from the same start"}
 
     if not args.no_configs and prec == 64:
         # the other timed workload configurations: 8^4 from a cold start, 32 sweeps (launch-bound: reported
@@ -335,7 +533,7 @@ def main():
         # sweep and, separately, only after the last; 64^4 at beta 6.0 in both precisions
         # (10 sweeps each after one untimed sweep); the double-layered torus with per-layer couplings
         # 5.5 / 6.2 (32 sweeps) with its Polyakov loops
-        out["configs"] = {
+        cfg = {
             "8^4_fp64_cold_beta5.7": config_rate(8, 1, 64, 5.7, 32, hot=False, untimed=0),
             "16^4_fp64_beta5.7": config_rate(16, 1, 64, 5.7, 32),
             "16^4_fp32_beta5.7": config_rate(16, 1, 32, 5.7, 32),
@@ -344,14 +542,30 @@ def main():
             "64^4_fp64_beta6.0": config_rate(64, 1, 64, 6.0, 10),
             "64^4_fp32_beta6.0": config_rate(64, 1, 32, 6.0, 10),
             "dlt_2x16^4_fp64_beta5.5|6.2": two_coupling_rate(16, 5.5, 6.2, 32)}
+        # each FP32 figure with its error against the FP64 chain of the same configuration (same seed,
+        # start and sweeps: the FP64 runs above)
+        for k32, k64 in (("16^4_fp32_beta5.7", "16^4_fp64_beta5.7"), ("64^4_fp32_beta6.0", "64^4_fp64_beta6.0")):
+            cfg[k32]["vs_fp64_chain"] = chain_deviation(cfg[k32]["_plaquette_series"], cfg[k64]["_plaquette_series"])
+        for v in cfg.values():
+            v.pop("_plaquette_series", None)
+        out["configs"] = cfg
 
     if not args.no_serving:
-        from paper_0904_1179_amd.serve import run_stream_benchmark
+        from paper_0904_1179_amd.serve import run_stream, run_stream_benchmark
+        from paper_0904_1179_amd.workloads import serving_stream
 
-        out["serving"] = run_stream_benchmark()
+        serving = run_stream_benchmark()
+        # saturation: the same 256 jobs all submitted at t = 0 (what the server sustains, not the offered load)
+        jobs = serving_stream(n_jobs=256, rate=20.0, seed=0, precision=32)
+        recs, sat = run_stream(jobs, arena_bytes=4 << 30, max_active=256, realtime=False)
+        serving["saturation"] = {k: sat[k] for k in ("wall_s", "throughput_updates_per_s", "p50_latency_s",
+                                                     "p99_latency_s", "steps", "arena_peak_bytes")}
+        serving["saturation"]["workload"] = "the same 256 jobs, all submitted at t = 0"
+        serving["fp32_vs_fp64"] = served_fp32_deviation(jobs, recs)
+        out["serving"] = serving
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(L, beta)
+        out["cpu_baseline"] = cpu_baseline(L, beta, configs=not args.no_cpu_configs)
 
     # the paper's own figures (CPU wall clock, FP64), as context only
     out["paper_context"] = {

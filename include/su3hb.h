@@ -51,7 +51,9 @@ typedef enum {
     SU3_EINVAL = -1,  /* invalid argument (parameters, sizes, null pointers, beta) */
     SU3_ENOSPC = -2,  /* a caller buffer is smaller than su3_footprint requires */
     SU3_EDEVICE = -3, /* HIP launch or runtime error */
-    SU3_ESTATE = -4   /* call out of order, e.g. sweep or plaquette before start */
+    SU3_ESTATE = -4,  /* call out of order, e.g. sweep or plaquette before start */
+    SU3_ENUMERIC = -5 /* the link data are not finite or not in SU(3): a property of the data, not
+                         a device fault; the call still completes and writes its outputs */
 } su3_status;
 
 typedef struct su3_ctx su3_ctx;
@@ -95,21 +97,36 @@ su3_status su3_create(const su3_params *p, void *d_links, size_t link_bytes, voi
  * links.  Resets the sweep counter and the heat-bath counters. */
 su3_status su3_start(su3_ctx *c, int32_t hot);
 
-/* Enqueue n >= 0 sweeps at coupling beta (finite, > 0).  The sweep counter
- * advances by n; it keys the random numbers, so sweep(a) then sweep(b) equals
- * sweep(a + b) bit for bit.  SU3_ESTATE before su3_start/su3_set_links. */
+/* Enqueue n >= 0 sweeps at coupling beta (finite, > 0): the nequi updating
+ * sweeps without measurements that the paper times (Sec. 2, eq. (1) and the
+ * paragraph after it; Tables 1-3 give the sweep counts per lattice).  One
+ * sweep is the eight checkerboard passes mu = 0..3 x parity (even, odd), each
+ * updating every link U_mu(x) of that parity once (4 V nlat updates per
+ * sweep, the paper's unit of "SU(3) matrix updates", Sec. 2.1).  The sweep
+ * counter advances by n; it keys the random numbers, so sweep(a) then
+ * sweep(b) equals sweep(a + b) bit for bit.  Asynchronous: the call only
+ * enqueues the 8 n pass kernels on the context's stream.  SU3_ESTATE before
+ * su3_start/su3_set_links; SU3_EINVAL for n < 0 or beta not finite and > 0. */
 su3_status su3_sweep(su3_ctx *c, int32_t n, double beta);
 
-/* n sweeps, each followed by a plaquette measurement, with one stream
- * synchronisation at the end (per 256 sweeps) instead of one per sweep:
- * out[k*(1+nlat) + 0] is the mean plaquette after sweep k, out[k*(1+nlat) + 1 + l]
- * that of layer l (as su3_plaquette).  n_out >= n * (1 + nlat).
- * On a single torus the last pass of each sweep (mu = 3, odd sites) also sums
- * Re Tr(U_new A) over its links, which is the sum of the final plaquettes in
- * the planes (0,3), (1,3), (2,3) (each contains exactly one odd-site link in
- * direction 3), and one kernel adds the planes (0,1), (0,2), (1,2); the value
- * equals su3_plaquette's up to rounding (U_new before its final
- * reunitarisation; products in the link precision, sums in FP64). */
+/* n sweeps, each followed by a plaquette measurement (the measurement
+ * routines the paper advises timing together with the sweeps, Sec. 2.2, last
+ * paragraph), with one stream synchronisation at the end (per 256 sweeps)
+ * instead of one per sweep: out[k*(1+nlat) + 0] is the mean plaquette after
+ * sweep k, out[k*(1+nlat) + 1 + l] that of layer l (as su3_plaquette).
+ * n_out >= n * (1 + nlat).
+ * No separate plaquette pass runs: after the odd pass of direction mu no
+ * later pass of the sweep changes U_nu or U_mu for nu < mu, so the odd passes
+ * of mu = 1, 2, 3 each also sum Re Tr(U_new S) over their links, S being the
+ * staple terms of the directions nu < mu, which is the final plaquette sum of
+ * the planes (nu, mu), nu < mu; the three passes give all six planes.  On a
+ * double-layered torus a plaquette based at x - nu lies in the other layer
+ * than x when that step crosses a flipped boundary; one more kernel sums
+ * those plaquettes so that each is filed under its base site's layer.  The
+ * value equals su3_plaquette's up to rounding (products in the link
+ * precision, before the final reunitarisation of the new link; sums in
+ * FP64).  SU3_ENUMERIC (outputs written) if a measured plaquette is not
+ * finite. */
 su3_status su3_sweep_measure(su3_ctx *c, int32_t n, double beta, double *out, size_t n_out);
 
 /* Double-layered torus only (nlat = 2, else SU3_EINVAL): n sweeps with
@@ -129,14 +146,24 @@ su3_status su3_sweep_betas(su3_ctx *c, int32_t n, double beta0, double beta1);
 su3_status su3_polyakov(su3_ctx *c, double *out, int32_t n);
 
 /* Mean plaquette 1/3 Re Tr U_P: out[0] over the whole lattice, out[1..nlat] per
- * layer (a plaquette belongs to the layer of its base site).  n >= 1 + nlat.
- * Accumulated in FP64 with a fixed reduction order (bitwise reproducible).
+ * layer (a plaquette belongs to the layer of its base site).  The paper's
+ * runs time sweeps without measurements (Sec. 2) and advise timing the
+ * measurement routines as well before production runs (Sec. 2.2, last
+ * paragraph); the plaquette is the basic one.  n >= 1 + nlat.  Accumulated in
+ * FP64 with a fixed reduction order (bitwise reproducible).  The same pass
+ * checks every link: SU3_ENUMERIC (out still written) if any link is not
+ * finite or its stored rows 0 and 1 are not orthonormal within 1e-10 (FP64
+ * links) or 1e-5 (FP32 links); the last-error text gives the count.
  * Synchronises the stream. */
 su3_status su3_plaquette(su3_ctx *c, double *out, int32_t n);
 
 /* Project every link back onto SU(3) (Gram-Schmidt of rows 0 and 1, row 2 =
- * conj(row0 x row1)), in FP64 for both precisions.  The heat bath already does
- * this for every link it updates. */
+ * conj(row0 x row1)), in FP64 for both precisions.  Not described in the
+ * paper, which stores 18 reals per link (App. A, eq. (4)) without saying how
+ * rounding drift off SU(3) is held back; here it is part of the method's
+ * specification, and the heat bath already applies it to every link it
+ * updates.  This call applies it to the whole lattice, e.g. after
+ * su3_set_links of data from elsewhere.  Asynchronous. */
 su3_status su3_reunitarise(su3_ctx *c);
 
 /* Copy the links to / from host memory in the canonical FP64 layout
@@ -162,7 +189,12 @@ su3_status su3_get_sweep_index(su3_ctx *c, uint64_t *sweep_index);
 su3_status su3_set_sweep_index(su3_ctx *c, uint64_t sweep_index);
 
 /* Sweeps done since start and Kennedy-Pendleton attempts / acceptances (exact
- * integer counts).  Any pointer may be NULL.  Synchronises the stream. */
+ * integer counts).  The paper quotes the acceptance rate of its 1-hit heat
+ * bath, 97.2 % at beta = 5.7 (Sec. 2.1); kp_accepts / kp_attempts is that
+ * rate.  Every SU(2) subgroup of every updated link makes nhit attempts at
+ * most and stops at its first acceptance, so with nhit = 1 kp_attempts is
+ * exactly 3 x 4 V nlat per sweep.  Any pointer may be NULL.  Synchronises the
+ * stream. */
 su3_status su3_counters(su3_ctx *c, uint64_t *sweeps, uint64_t *kp_attempts, uint64_t *kp_accepts);
 
 /* Random gauge transformation U_mu(x) -> g(x) U_mu(x) g(x+mu)^+ with Haar g
@@ -219,6 +251,7 @@ typedef struct {
     double plaquette[3];  /* once done: total, then per layer (as su3_plaquette) */
     uint64_t kp_attempts; /* once done */
     uint64_t kp_accepts;
+    int64_t bad_links;    /* once done: links failing the check of su3_plaquette (0 for a healthy chain) */
 } su3_job_result;
 
 /* d_arena: device buffer of arena_bytes, 256-byte aligned; the server keeps
@@ -239,6 +272,12 @@ su3_status su3_server_step(su3_server *s, int32_t *n_active, int32_t *n_queued, 
 su3_status su3_server_run(su3_server *s, int32_t max_sweeps, int32_t *n_active, int32_t *n_queued,
                           int32_t *n_finished);
 su3_status su3_server_poll(su3_server *s, int64_t job_id, su3_job_result *out);
+/* Copy an active job's links to host memory in the canonical FP64 layout of
+ * su3_get_links (n_doubles = 72 V nlat of the job), between server calls:
+ * the read-back for checking a served job link by link.  SU3_ESTATE if the
+ * job is queued or done (its links are then not on the device).
+ * Synchronises the server's stream. */
+su3_status su3_server_get_links(su3_server *s, int64_t job_id, double *host, size_t n_doubles);
 su3_status su3_server_stats(su3_server *s, size_t *arena_used, size_t *arena_peak, uint64_t *steps);
 /* Waits for the stream, frees host resources; never frees the arena. */
 su3_status su3_server_destroy(su3_server *s);

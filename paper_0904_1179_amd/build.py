@@ -13,12 +13,19 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsu3hb.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "api.hip", "server.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "api.hip", "server.hip", "layout.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMPILE = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I" + os.path.join(ROOT, "include")]
+# layout.cpp is plain host C++ (no device code)
+COMPILE_CXX = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include")]
+
+
+def _compile_cmd(src, obj):
+    flags = COMPILE_CXX if src.endswith(".cpp") else COMPILE
+    return [HIPCC] + flags + ["-c", src, "-o", obj]
 
 
 def _run(cmd, tmpdir=None):
@@ -39,7 +46,7 @@ def build() -> str:
         objs = [os.path.join(tmp, os.path.basename(s) + ".o") for s in SOURCES]
         with ThreadPoolExecutor(max_workers=len(SOURCES)) as pool:
             list(pool.map(lambda c: _run(c, tmp),
-                          [[HIPCC] + COMPILE + ["-c", src, "-o", obj] for src, obj in zip(SOURCES, objs)]))
+                          [_compile_cmd(src, obj) for src, obj in zip(SOURCES, objs)]))
         out = LIB + ".tmp"
         _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out] + objs, tmp)
         os.replace(out, LIB)

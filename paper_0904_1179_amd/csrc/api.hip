@@ -37,131 +37,9 @@ struct su3_ctx {
 
 namespace su3hb {
 
-namespace {
-thread_local std::string g_last_error;
-long long round_up(long long a, long long m) { return (a + m - 1) / m * m; }
-}  // namespace
-
-su3_status fail(su3_status s, const std::string &msg)
-{
-    g_last_error = msg;
-    return s;
-}
-
 su3_status hip_fail(hipError_t e, const char *where)
 {
     return fail(SU3_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
-}
-
-const char *last_error() { return g_last_error.c_str(); }
-
-su3_status check_params(const su3_params *p)
-{
-    if (!p) return fail(SU3_EINVAL, "params is NULL");
-    for (int mu = 0; mu < 4; ++mu) {
-        const int L = p->L[mu];
-        if (L < 2 || L > 1024 || (L & 1))
-            return fail(SU3_EINVAL, "L[" + std::to_string(mu) + "] = " + std::to_string(L) +
-                                        ": extents must be even and in [2, 1024]");
-    }
-    if (p->nlat != 1 && p->nlat != 2) return fail(SU3_EINVAL, "nlat must be 1 (torus) or 2 (double-layered torus)");
-    if (p->nlat == 1 && p->flip_mask != 0) return fail(SU3_EINVAL, "flip_mask must be 0 when nlat = 1");
-    if (p->flip_mask > 0xF) return fail(SU3_EINVAL, "flip_mask has bits above direction 3");
-    if (p->precision != 64 && p->precision != 32) return fail(SU3_EINVAL, "precision must be 64 or 32");
-    if (p->nhit < 1 || p->nhit > 64) return fail(SU3_EINVAL, "nhit must be in [1, 64]");
-    const long long V = (long long)p->L[0] * p->L[1] * p->L[2] * p->L[3];
-    if ((long long)p->nlat * V > (1LL << 30))
-        return fail(SU3_EINVAL, "lattice too large: nlat*V must not exceed 2^30 sites");
-    return SU3_OK;
-}
-
-// Domains of the pass order (the (x1, x2) cross-section cut into w1 x w2
-// pieces, each swept along x3).  A link on a domain's rim is read by two
-// XCDs, each from HBM, so the choice takes the fewest rim links, the sum of
-// 1/w over the directions that are cut, among the widths that
-//  * give every XCD whole domains: nd * nlat a multiple of 8, nd = (L1/w1)(L2/w2);
-//  * keep one x3 slab of a domain within kSlabMax = 4096 updates
-//    (L0/2 w1 w2 <= 4096), so that the links around it are re-read while
-//    still in L2;
-//  * keep the lanes of a wave on whole 16-link tiles: L0/2 w1 a multiple of 16,
-//    or w1 = L1.
-// Ties go to the wider w1 (longer runs of consecutive links).  Without such
-// widths the rule keeps w1 = L1 and the largest w2 <= L2/8.
-void pick_domains(const int32_t L[4], int nlat, int &w1, int &w2)
-{
-    constexpr long long kSlabMax = 4096;
-    const int l0h = L[0] / 2;
-    double best = 1e30;
-    w1 = L[1];
-    w2 = 0;
-    for (int a = L[1]; a >= 1; --a) {
-        if (L[1] % a || (a != L[1] && (l0h * a) % 16)) continue;
-        for (int b = L[2]; b >= 1; --b) {
-            if (L[2] % b) continue;
-            const long long nd = (long long)(L[1] / a) * (L[2] / b) * nlat;
-            if (nd % 8 || (long long)l0h * a * b > kSlabMax) continue;
-            const double rim = (a < L[1] ? 1.0 / a : 0.0) + (b < L[2] ? 1.0 / b : 0.0);
-            if (rim < best - 1e-12) {
-                best = rim;
-                w1 = a;
-                w2 = b;
-            }
-        }
-    }
-    if (w2 == 0) {
-        w1 = L[1];
-        w2 = 1;
-        for (int b = 1; b <= L[2] / 8; ++b)
-            if (L[2] % b == 0) w2 = b;
-    }
-}
-
-Geom make_geom(const su3_params *p)
-{
-    su3hb::Geom g;
-    for (int mu = 0; mu < 4; ++mu) g.L[mu] = p->L[mu];
-    const long long V = (long long)p->L[0] * p->L[1] * p->L[2] * p->L[3];
-    g.Vh = (int)(V / 2);
-    g.nlat = p->nlat;
-    g.flip = p->nlat == 2 ? p->flip_mask : 0u;
-    // +64: the (direction, parity) blocks are offset by 64 links from a large
-    // power-of-two spacing, so equal positions in different blocks do not all
-    // fall in the same L2 channel and set
-    g.stride = round_up((long long)p->nlat * (V / 2), 64) + 64;
-    pick_domains(p->L, p->nlat, g.w1, g.w2);
-    g.nd1 = p->L[1] / g.w1;
-    g.dl0h = su3hb::make_fastdiv((uint32_t)(p->L[0] / 2));
-    g.dl1 = su3hb::make_fastdiv((uint32_t)p->L[1]);
-    g.dl2 = su3hb::make_fastdiv((uint32_t)p->L[2]);
-    g.dl3 = su3hb::make_fastdiv((uint32_t)p->L[3]);
-    g.dw1 = su3hb::make_fastdiv((uint32_t)g.w1);
-    g.dw2 = su3hb::make_fastdiv((uint32_t)g.w2);
-    g.dnd1 = su3hb::make_fastdiv((uint32_t)g.nd1);
-    return g;
-}
-
-size_t link_bytes_of(const su3_params *p, const Geom &g)
-{
-    // 8 (direction, parity) blocks of `stride` links, 6 complex entries each
-    return (size_t)8 * su3hb::kEntries * (size_t)g.stride * (p->precision == 64 ? 16u : 8u);
-}
-
-size_t meas_offset(const Geom &g) { return (size_t)round_up(kOffPartials + 8LL * g.nlat * plaq_blocks(g), 256); }
-
-size_t faces_offset(const Geom &g)
-{
-    return (size_t)round_up((long long)meas_offset(g) + 3 * 8LL * g.nlat * meas_blocks(g), 256);
-}
-
-size_t polyakov_offset(const Geom &g)
-{
-    const long long faces = g.nlat == 2 ? 2 * su3hb::kFaceGroups * 8LL * face_blocks(g) : 0;
-    return (size_t)round_up((long long)faces_offset(g) + faces, 256);
-}
-
-size_t scratch_bytes_of(const Geom &g)
-{
-    return (size_t)round_up((long long)polyakov_offset(g) + 16LL * g.nlat * polyakov_blocks(g), 256);
 }
 
 }  // namespace su3hb
@@ -184,47 +62,6 @@ su3_status check_started(su3_ctx *c)
 
 unsigned long long *counters_of(su3_ctx *c) { return (unsigned long long *)(c->scratch + kOffCounters); }
 
-// device element index of entry e of link n of block (dir, par), in complex numbers
-// 18 reals of a link in the host layout (row-major, re/im): row 2 from rows 0
-// and 1 as conj(row 0 x row 1), the formula the kernels use
-void rebuild_row2_host(double *m)
-{
-    for (int k = 0; k < 3; ++k) {
-        const int a = (k + 1) % 3, b = (k + 2) % 3;
-        const double p_re = m[2 * a] * m[6 + 2 * b] - m[2 * a + 1] * m[6 + 2 * b + 1];
-        const double p_im = m[2 * a] * m[6 + 2 * b + 1] + m[2 * a + 1] * m[6 + 2 * b];
-        const double q_re = m[2 * b] * m[6 + 2 * a] - m[2 * b + 1] * m[6 + 2 * a + 1];
-        const double q_im = m[2 * b] * m[6 + 2 * a + 1] + m[2 * b + 1] * m[6 + 2 * a];
-        m[12 + 2 * k] = p_re - q_re;
-        m[12 + 2 * k + 1] = -(p_im - q_im);
-    }
-}
-
-size_t dev_index(const Geom &g, int dir, int par, int e, long long n)
-{
-    using su3hb::kEntries;
-    using su3hb::kTile;
-    return (size_t)(dir * 2 + par) * (size_t)g.stride * kEntries + (size_t)(n >> 4) * (kEntries * kTile) +
-           (size_t)e * kTile + (size_t)(n & (kTile - 1));
-}
-
-// canonical host index of the plane element (dir, par, e, n): maps (layer, parity, i) to site
-void site_of_elem(const Geom &g, int par, long long n, long long *site)
-{
-    const int layer = n >= g.Vh ? 1 : 0;
-    long long i = n - (long long)layer * g.Vh;
-    const int l0h = g.L[0] / 2;
-    long long r = i / l0h;
-    const int x0h = (int)(i - r * l0h);
-    const int x1 = (int)(r % g.L[1]);
-    r /= g.L[1];
-    const int x2 = (int)(r % g.L[2]);
-    const int x3 = (int)(r / g.L[2]);
-    const int x0 = 2 * x0h + ((par + x1 + x2 + x3) & 1);
-    const long long lex = x0 + (long long)g.L[0] * (x1 + (long long)g.L[1] * (x2 + (long long)g.L[2] * x3));
-    *site = (long long)layer * 2LL * g.Vh + lex;
-}
-
 }  // namespace
 
 extern "C" {
@@ -237,6 +74,7 @@ const char *su3_strerror(su3_status s)
     case SU3_ENOSPC: return "buffer smaller than the footprint";
     case SU3_EDEVICE: return "HIP device error";
     case SU3_ESTATE: return "call out of order";
+    case SU3_ENUMERIC: return "non-finite or non-unitary link data";
     }
     return "unknown status";
 }
@@ -304,7 +142,7 @@ su3_status su3_start(su3_ctx *c, int32_t hot)
     if (hot != 0 && hot != 1) return fail(SU3_EINVAL, "hot must be 0 (cold) or 1 (hot)");
     hipError_t e = su3hb::launch_start(c->p.precision, c->links, c->g, hot, c->p.seed, c->stream);
     if (e != hipSuccess) return hip_fail(e, "start kernel");
-    e = su3hb::launch_zero_u64(counters_of(c), 2 * su3hb::kCounterSlots, c->stream);
+    e = su3hb::launch_zero_u64(counters_of(c), 2 * kCounterSlots, c->stream);
     if (e != hipSuccess) return hip_fail(e, "counter reset");
     c->started = true;
     c->sweep_index = 0;
@@ -429,6 +267,7 @@ su3_status su3_sweep_measure(su3_ctx *c, int32_t n, double beta, double *out, si
     double *slots = (double *)(c->scratch + kOffMeasure);
     std::vector<double> h((size_t)kMeasureChunk * 4);
     const double norm = 18.0 * (double)c->V;
+    su3_status bad = SU3_OK;
     for (int32_t done = 0; done < n;) {
         const int32_t m = std::min<int32_t>(kMeasureChunk, n - done);
         for (int32_t k = 0; k < m; ++k) {
@@ -452,10 +291,13 @@ su3_status su3_sweep_measure(su3_ctx *c, int32_t n, double beta, double *out, si
             double *o = out + (size_t)(done + k) * w;
             o[0] = h[4 * k] / (norm * c->p.nlat);
             for (int l = 0; l < c->p.nlat; ++l) o[1 + l] = h[4 * k + 1 + l] / norm;
+            if (!std::isfinite(o[0]) && !bad)
+                bad = fail(SU3_ENUMERIC, "plaquette after sweep " + std::to_string(done + k) +
+                                             " of this call is not finite: the lattice holds non-finite links");
         }
         done += m;
     }
-    return SU3_OK;
+    return bad ? SU3_ENUMERIC : SU3_OK;
 }
 
 }  // extern "C"
@@ -471,14 +313,19 @@ su3_status su3_plaquette(su3_ctx *c, double *out, int32_t n)
     double *partials = (double *)(c->scratch + kOffPartials);
     hipError_t e = su3hb::launch_plaquette(c->p.precision, c->links, c->g, partials, sums, c->stream);
     if (e != hipSuccess) return hip_fail(e, "plaquette kernels");
-    double h[3] = {0, 0, 0};
-    e = hipMemcpyAsync(h, sums, sizeof(double) * (1 + c->p.nlat), hipMemcpyDeviceToHost, c->stream);
+    double h[4] = {0, 0, 0, 0};
+    e = hipMemcpyAsync(h, sums, sizeof(h), hipMemcpyDeviceToHost, c->stream);
     if (e != hipSuccess) return hip_fail(e, "plaquette copy");
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "plaquette sync");
     const double norm = 18.0 * (double)c->V;
     out[0] = h[0] / (norm * c->p.nlat);
     for (int l = 0; l < c->p.nlat; ++l) out[1 + l] = h[1 + l] / norm;
+    if (h[3] != 0.0 || !std::isfinite(out[0]))
+        return fail(SU3_ENUMERIC, std::to_string((long long)h[3]) +
+                                      " links are not finite or have rows 0, 1 that are not orthonormal within " +
+                                      std::to_string(unitarity_tol(c->p.precision)) + "; plaquette " +
+                                      std::to_string(out[0]));
     return SU3_OK;
 }
 
@@ -513,40 +360,17 @@ su3_status su3_get_links(su3_ctx *c, double *host, size_t n_doubles)
     if (n_doubles != need) return fail(SU3_EINVAL, "n_doubles must be 72*V*nlat = " + std::to_string(need));
     st = check_started(c);
     if (st != SU3_OK) return st;
-    const Geom &g = c->g;
-    const size_t bytes = link_bytes_of(&c->p, g);
     std::vector<unsigned char> buf;
     try {
-        buf.resize(bytes);
+        buf.resize(link_bytes_of(&c->p, c->g));
     } catch (...) {
         return fail(SU3_EINVAL, "out of host memory for the staging copy");
     }
-    hipError_t e = hipMemcpyAsync(buf.data(), c->links, bytes, hipMemcpyDeviceToHost, c->stream);
+    hipError_t e = hipMemcpyAsync(buf.data(), c->links, buf.size(), hipMemcpyDeviceToHost, c->stream);
     if (e != hipSuccess) return hip_fail(e, "link copy");
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "link copy sync");
-    const long long nelem = (long long)g.nlat * g.Vh;
-    for (int par = 0; par < 2; ++par)
-        for (long long n = 0; n < nelem; ++n) {
-            long long site;
-            site_of_elem(g, par, n, &site);
-            for (int dir = 0; dir < 4; ++dir) {
-                double *dst = host + (size_t)(4 * site + dir) * 18;
-                for (int el = 0; el < su3hb::kEntries; ++el) {
-                    const size_t idx = dev_index(g, dir, par, el, n);
-                    if (c->p.precision == 64) {
-                        const double *v = (const double *)buf.data() + 2 * idx;
-                        dst[2 * el] = v[0];
-                        dst[2 * el + 1] = v[1];
-                    } else {
-                        const float *v = (const float *)buf.data() + 2 * idx;
-                        dst[2 * el] = (double)v[0];
-                        dst[2 * el + 1] = (double)v[1];
-                    }
-                }
-                rebuild_row2_host(dst);
-            }
-        }
+    unpack_links(c->p.precision, c->g, buf.data(), host);
     return SU3_OK;
 }
 
@@ -557,41 +381,20 @@ su3_status su3_set_links(su3_ctx *c, const double *host, size_t n_doubles)
     if (!host) return fail(SU3_EINVAL, "host buffer is NULL");
     const size_t need = (size_t)72 * c->V * c->p.nlat;
     if (n_doubles != need) return fail(SU3_EINVAL, "n_doubles must be 72*V*nlat = " + std::to_string(need));
-    const Geom &g = c->g;
-    const size_t bytes = link_bytes_of(&c->p, g);
+    const size_t bytes = link_bytes_of(&c->p, c->g);
     std::vector<unsigned char> buf;
     try {
         buf.assign(bytes, 0);
     } catch (...) {
         return fail(SU3_EINVAL, "out of host memory for the staging copy");
     }
-    const long long nelem = (long long)g.nlat * g.Vh;
-    for (int par = 0; par < 2; ++par)
-        for (long long n = 0; n < nelem; ++n) {
-            long long site;
-            site_of_elem(g, par, n, &site);
-            for (int dir = 0; dir < 4; ++dir) {
-                const double *src = host + (size_t)(4 * site + dir) * 18;
-                for (int el = 0; el < su3hb::kEntries; ++el) {
-                    const size_t idx = dev_index(g, dir, par, el, n);
-                    if (c->p.precision == 64) {
-                        double *v = (double *)buf.data() + 2 * idx;
-                        v[0] = src[2 * el];
-                        v[1] = src[2 * el + 1];
-                    } else {
-                        float *v = (float *)buf.data() + 2 * idx;
-                        v[0] = (float)src[2 * el];
-                        v[1] = (float)src[2 * el + 1];
-                    }
-                }
-            }
-        }
+    pack_links(c->p.precision, c->g, host, buf.data());
     hipError_t e = hipMemcpyAsync(c->links, buf.data(), bytes, hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(e, "link copy");
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "link copy sync");
     if (!c->started) {
-        e = su3hb::launch_zero_u64(counters_of(c), 2 * su3hb::kCounterSlots, c->stream);
+        e = su3hb::launch_zero_u64(counters_of(c), 2 * kCounterSlots, c->stream);
         if (e != hipSuccess) return hip_fail(e, "counter reset");
     }
     c->started = true;
@@ -607,30 +410,21 @@ su3_status su3_get_link_sample(su3_ctx *c, const uint64_t *lids, size_t n, doubl
     st = check_started(c);
     if (st != SU3_OK) return st;
     const Geom &g = c->g;
-    const uint64_t nlinks = 4ull * c->V * (uint64_t)c->p.nlat;
     const size_t esz = c->p.precision == 64 ? 16 : 8;
     std::vector<unsigned char> buf;
     try {
-        buf.resize(n * su3hb::kEntries * esz);
+        buf.resize(n * kEntries * esz);
     } catch (...) {
         return fail(SU3_EINVAL, "out of host memory for the sample");
     }
     for (size_t k = 0; k < n; ++k) {
-        if (lids[k] >= nlinks) return fail(SU3_EINVAL, "link id " + std::to_string(lids[k]) + " out of range");
-        const uint64_t site = lids[k] / 4;
-        const int dir = (int)(lids[k] % 4);
-        const int layer = (int)(site / c->V);
-        uint64_t lex = site % c->V;
-        int x[4];
-        for (int mu = 0; mu < 4; ++mu) {
-            x[mu] = (int)(lex % (uint64_t)g.L[mu]);
-            lex /= (uint64_t)g.L[mu];
-        }
-        const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
-        const size_t elem = (size_t)layer * (size_t)g.Vh + (size_t)((site % c->V) >> 1);
-        for (int el = 0; el < su3hb::kEntries; ++el) {
-            const size_t idx = dev_index(g, dir, par, el, (long long)elem);
-            hipError_t e = hipMemcpyAsync(buf.data() + (k * su3hb::kEntries + el) * esz,
+        int dir, par;
+        long long elem;
+        if (!elem_of_lid(g, lids[k], &dir, &par, &elem))
+            return fail(SU3_EINVAL, "link id " + std::to_string(lids[k]) + " out of range");
+        for (int el = 0; el < kEntries; ++el) {
+            const size_t idx = dev_index(g, dir, par, el, elem);
+            hipError_t e = hipMemcpyAsync(buf.data() + (k * kEntries + el) * esz,
                                           (const unsigned char *)c->links + idx * esz, esz, hipMemcpyDeviceToHost,
                                           c->stream);
             if (e != hipSuccess) return hip_fail(e, "sample copy");
@@ -640,8 +434,8 @@ su3_status su3_get_link_sample(su3_ctx *c, const uint64_t *lids, size_t n, doubl
     if (e != hipSuccess) return hip_fail(e, "sample sync");
     for (size_t k = 0; k < n; ++k) {
         double *dst = host + 18 * k;
-        for (int el = 0; el < su3hb::kEntries; ++el) {
-            const size_t i = k * su3hb::kEntries + el;
+        for (int el = 0; el < kEntries; ++el) {
+            const size_t i = k * kEntries + el;
             if (c->p.precision == 64) {
                 dst[2 * el] = ((const double *)buf.data())[2 * i];
                 dst[2 * el + 1] = ((const double *)buf.data())[2 * i + 1];
@@ -678,14 +472,14 @@ su3_status su3_counters(su3_ctx *c, uint64_t *sweeps, uint64_t *kp_attempts, uin
     if (st != SU3_OK) return st;
     st = check_started(c);
     if (st != SU3_OK) return st;
-    std::vector<unsigned long long> h(2 * su3hb::kCounterSlots);
+    std::vector<unsigned long long> h(2 * kCounterSlots);
     hipError_t e = hipMemcpyAsync(h.data(), counters_of(c), h.size() * sizeof(unsigned long long),
                                   hipMemcpyDeviceToHost, c->stream);
     if (e != hipSuccess) return hip_fail(e, "counter copy");
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "counter sync");
     unsigned long long att = 0, acc = 0;
-    for (int k = 0; k < su3hb::kCounterSlots; ++k) {
+    for (int k = 0; k < kCounterSlots; ++k) {
         att += h[2 * k];
         acc += h[2 * k + 1];
     }

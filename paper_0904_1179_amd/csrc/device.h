@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "geom.h"
+
 namespace su3hb {
 
 // ---------------------------------------------------------------------------
@@ -320,8 +322,6 @@ __device__ __forceinline__ double unif32(uint32_t h) { return (double(h) + 0.5) 
 // [k * n/8, (k+1) * n/8) keeps neighbouring tiles, which share staple links,
 // on one L2.  A bijection for any n.
 // ---------------------------------------------------------------------------
-constexpr int kNumXcd = 8;
-
 __device__ __forceinline__ int xcd_tile(int b, int n)
 {
     const int xcd = b % kNumXcd, local = b / kNumXcd;
@@ -332,48 +332,6 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
 // ---------------------------------------------------------------------------
 // lattice geometry
 // ---------------------------------------------------------------------------
-// Sites are addressed by (layer, parity, i): i = lex >> 1 with
-// lex = x0 + L0 (x1 + L1 (x2 + L2 x3)); with L0 even, the two sites sharing
-// lex >> 1 have opposite parity.  Within a (direction, parity) block the
-// link of site (layer, parity, i) is element n = layer * Vh + i.
-// Unsigned division by a divisor fixed for a launch (Granlund and Montgomery,
-// "Division by invariant integers using multiplication", 1994): with
-// l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1, s1 = min(l, 1),
-// s2 = max(l - 1, 0) and t = floor(m x / 2^32),
-//   floor(x / d) = (t + ((x - t) >> s1)) >> s2   for every 0 <= x < 2^32,
-// a multiply-high and three shifts/adds instead of a division sequence.
-struct FastDiv {
-    uint32_t d, m, s1, s2;
-};
-inline FastDiv make_fastdiv(uint32_t d)
-{
-    uint32_t l = 0;
-    while ((1ull << l) < d) ++l;
-    FastDiv f;
-    f.d = d;
-    f.m = (uint32_t)((((uint64_t)1 << 32) * ((1ull << l) - d)) / d + 1);
-    f.s1 = l < 1 ? l : 1;
-    f.s2 = l > 1 ? l - 1 : 0;
-    return f;
-}
-__host__ __device__ __forceinline__ int div_by(int x, const FastDiv &f)
-{
-    const uint32_t ux = (uint32_t)x;
-    const uint32_t t = (uint32_t)(((uint64_t)f.m * ux) >> 32);
-    return (int)((t + ((ux - t) >> f.s1)) >> f.s2);
-}
-
-struct Geom {
-    int L[4];
-    int Vh;             // V / 2
-    int nlat;
-    unsigned flip;      // layer-switch mask, 0 on a single torus
-    long long stride;   // links per (direction, parity) block (>= nlat * Vh, multiple of 64)
-    int w1, w2;         // domain widths of the pass order (divide L1, L2)
-    int nd1;            // L1 / w1
-    FastDiv dl0h, dl1, dl2, dl3, dw1, dw2, dnd1;  // division by L0/2, L1, L2, L3, w1, w2, nd1
-};
-
 // Coordinates of the site with parity `par` and half-index i.
 __device__ __forceinline__ void site_coords(const Geom &g, int par, int i, int x[4])
 {
@@ -474,9 +432,6 @@ __device__ __forceinline__ int order_index(const Geom &g, int v)
 // per tile and entry: whole cache lines.  The 6 loads of one link share a
 // single per-lane address and differ by the compile-time offset e * 16
 // elements, which the load instruction encodes as an immediate.
-constexpr int kTile = 16;
-constexpr int kEntries = 6;
-
 template <typename R>
 __device__ __forceinline__ const store_t<R> *planes(const store_t<R> *links, const Geom &g, int dir, int par)
 {

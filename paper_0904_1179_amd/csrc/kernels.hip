@@ -653,7 +653,24 @@ __device__ __forceinline__ double plaq_plane_own(const store_t<R> *__restrict__ 
     return s;
 }
 
-// The six planes of the site.
+// 1 if the stored rows 0 and 1 of u are not finite or not orthonormal within
+// tol (|r0|^2 - 1, |r1|^2 - 1, <r0, r1>), else 0.  Row 2 is conj(r0 x r1), so
+// orthonormal rows 0 and 1 make u an SU(3) matrix.  NaN fails every test.
+__device__ __forceinline__ int link_bad(const M3<double> &u, double tol)
+{
+    double n0 = 0.0, n1 = 0.0;
+    Cx<double> d{0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        n0 += u.e[0][k].re * u.e[0][k].re + u.e[0][k].im * u.e[0][k].im;
+        n1 += u.e[1][k].re * u.e[1][k].re + u.e[1][k].im * u.e[1][k].im;
+        d = cmadd_cn(d, u.e[0][k], u.e[1][k]);
+    }
+    const bool ok = fabs(n0 - 1.0) <= tol && fabs(n1 - 1.0) <= tol && fabs(d.re) <= tol && fabs(d.im) <= tol;
+    return ok ? 0 : 1;
+}
+
+// The six planes of the site, and the check of its four own links.
 //  * FP64: every plane loads its four links; the compiler issues the loads of
 //    both sites of a thread at once (one wave per SIMD).
 //  * FP32: the four own links are loaded once and kept, and compiler-only
@@ -662,7 +679,7 @@ __device__ __forceinline__ double plaq_plane_own(const store_t<R> *__restrict__ 
 //    same time with 31 % more bytes fetched.
 template <typename R, bool DLT>
 __device__ __forceinline__ double plaq_site(const store_t<R> *__restrict__ links, const Geom &g, int layer, int par,
-                                           int i)
+                                           int i, double tol, int &bad)
 {
     int x[4];
     site_coords(g, par, i, x);
@@ -674,11 +691,16 @@ __device__ __forceinline__ double plaq_site(const store_t<R> *__restrict__ links
         s += plaq_plane<0, 3, R, DLT>(links, g, x, layer, par, n);
         s += plaq_plane<1, 3, R, DLT>(links, g, x, layer, par, n);
         s += plaq_plane<2, 3, R, DLT>(links, g, x, layer, par, n);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) bad += link_bad(load_rows01<R>(planes<R>(links, g, mu, par), n), tol);
         return s;
     } else {
         M3<double> U[4];
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu) U[mu] = load_rows01<R>(planes<R>(links, g, mu, par), n);
+        for (int mu = 0; mu < 4; ++mu) {
+            U[mu] = load_rows01<R>(planes<R>(links, g, mu, par), n);
+            bad += link_bad(U[mu], tol);
+        }
         double s = plaq_plane_own<0, 1, R, DLT>(links, g, x, layer, par, U);
         stash_fence();
         s += plaq_plane_own<0, 2, R, DLT>(links, g, x, layer, par, U);
@@ -700,24 +722,32 @@ __device__ __forceinline__ double plaq_site(const store_t<R> *__restrict__ links
 // takes both sites with half-index i(v) (x0 neighbours), so the links of both
 // parities around a domain are read while they are in that XCD's L2.  Fixed
 // per-thread order, wave shuffles and a fixed per-block order: the sum is
-// bitwise reproducible.
+// bitwise reproducible.  partials[l nblk + b]: plaquette sum of workgroup b
+// of layer l; partials[(nlat + l) nblk + b]: its number of failing links.
 template <typename R, bool DLT>
 __global__ __launch_bounds__(kBlock) void k_plaq_partial(const store_t<R> *__restrict__ links, const Geom g,
-                                                         const int tiles_per_block, double *__restrict__ partials)
+                                                         const int tiles_per_block, const double tol,
+                                                         double *__restrict__ partials)
 {
     const int layer = DLT ? (int)blockIdx.y : 0;
     const int b = xcd_tile(blockIdx.x, gridDim.x);
     double s = 0.0;
+    int bad = 0;
     for (int t = 0; t < tiles_per_block; ++t) {
         const int v = (b * tiles_per_block + t) * kBlock + threadIdx.x;
         if (v < g.Vh) {
             const int i = order_index(g, v);
-            s += plaq_site<R, DLT>(links, g, layer, 0, i);
-            s += plaq_site<R, DLT>(links, g, layer, 1, i);
+            s += plaq_site<R, DLT>(links, g, layer, 0, i, tol, bad);
+            s += plaq_site<R, DLT>(links, g, layer, 1, i, tol, bad);
         }
     }
     const double bs = block_sum(s);
-    if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = bs;
+    __syncthreads();
+    const double bb = block_sum((double)bad);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.y * gridDim.x + blockIdx.x] = bs;
+        partials[(gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = bb;
+    }
 }
 
 // Double-layered torus, fused measurement: the measured odd pass of MU files
@@ -814,7 +844,8 @@ __global__ __launch_bounds__(kBlock) void k_measure_final_dlt(const double *__re
     }
 }
 
-// sums[1 + l] = sum over the partials of layer l; sums[0] = sum over layers
+// sums[1 + l] = sum over the partials of layer l; sums[0] = sum over layers;
+// sums[3] = number of links that failed the unitarity check
 __global__ __launch_bounds__(kBlock) void k_plaq_final(const double *__restrict__ partials, int nblk, int nlat,
                                                        double *__restrict__ sums)
 {
@@ -829,7 +860,14 @@ __global__ __launch_bounds__(kBlock) void k_plaq_final(const double *__restrict_
             tot += r;
         }
     }
-    if (threadIdx.x == 0) sums[0] = tot;
+    double nb = 0.0;
+    for (int b = threadIdx.x; b < nlat * nblk; b += kBlock) nb += partials[nlat * nblk + b];
+    const double r = block_sum(nb);
+    if (threadIdx.x == 0) {
+        sums[0] = tot;
+        if (nlat == 1) sums[2] = 0.0;
+        sums[3] = r;
+    }
 }
 
 // single torus: sums[0] = sums[1] = sum of the partials a[0..na), fixed order
@@ -871,16 +909,9 @@ __global__ __launch_bounds__(kBlock) void k_copy(const uint4 *__restrict__ src, 
 }
 
 inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
-// workgroups of nb threads covering the nlat * Vh links of one pass
-inline unsigned pass_blocks(const Geom &g, int nb) { return (unsigned)(((long long)g.nlat * g.Vh + nb - 1) / nb); }
 
 }  // namespace
 
-int plaq_blocks(const Geom &g)
-{
-    const long long need = ((long long)g.Vh + kBlock - 1) / kBlock;
-    return (int)(need < kPlaqBlocksMax ? need : kPlaqBlocksMax);
-}
 
 hipError_t launch_start(int precision, void *links, const Geom &g, int hot, uint64_t seed, hipStream_t s)
 {
@@ -1005,15 +1036,6 @@ static void update_meas_dispatch(store_t<R> *links, const Geom &g, int mu, doubl
     }
 }
 
-int meas_block_size(const Geom &g) { return g.nlat == 1 ? kPassBlock : kBlock; }
-int meas_blocks(const Geom &g) { return (int)pass_blocks(g, meas_block_size(g)); }
-
-int face_blocks(const Geom &g)
-{
-    const int lmin = std::min(std::min(g.L[0], g.L[1]), g.L[2]);
-    return (int)blocks_for((long long)g.nlat * (2LL * g.Vh / lmin));
-}
-
 hipError_t launch_plaq_faces(int precision, const void *links, const Geom &g, double *partials, hipStream_t s)
 {
     const dim3 grid(face_blocks(g), kFaceGroups);
@@ -1053,16 +1075,17 @@ hipError_t launch_plaquette(int precision, const void *links, const Geom &g, dou
     const int tpb = (int)((tiles + nblk - 1) / nblk);
     const dim3 grid(nblk, g.nlat);
     const bool dlt = g.nlat == 2;
+    const double tol = unitarity_tol(precision);
     if (precision == 64) {
         if (dlt)
-            k_plaq_partial<double, true><<<grid, kBlock, 0, s>>>((const double2 *)links, g, tpb, partials);
+            k_plaq_partial<double, true><<<grid, kBlock, 0, s>>>((const double2 *)links, g, tpb, tol, partials);
         else
-            k_plaq_partial<double, false><<<grid, kBlock, 0, s>>>((const double2 *)links, g, tpb, partials);
+            k_plaq_partial<double, false><<<grid, kBlock, 0, s>>>((const double2 *)links, g, tpb, tol, partials);
     } else {
         if (dlt)
-            k_plaq_partial<float, true><<<grid, kBlock, 0, s>>>((const float2 *)links, g, tpb, partials);
+            k_plaq_partial<float, true><<<grid, kBlock, 0, s>>>((const float2 *)links, g, tpb, tol, partials);
         else
-            k_plaq_partial<float, false><<<grid, kBlock, 0, s>>>((const float2 *)links, g, tpb, partials);
+            k_plaq_partial<float, false><<<grid, kBlock, 0, s>>>((const float2 *)links, g, tpb, tol, partials);
     }
     k_plaq_final<<<1, kBlock, 0, s>>>(partials, nblk, g.nlat, sums);
     return hipGetLastError();
@@ -1101,8 +1124,6 @@ hipError_t launch_update_twob(int precision, void *links, const Geom &g, int mu,
         twob_dispatch<float>((float2 *)links, g, mu, par, beta0, beta1, sweep, seed, nhit, counters, s);
     return hipGetLastError();
 }
-
-int polyakov_blocks(const Geom &g) { return (int)blocks_for((long long)g.L[0] * g.L[1] * g.L[2]); }
 
 hipError_t launch_polyakov(int precision, const void *links, const Geom &g, double *partials, double *out,
                            hipStream_t s)

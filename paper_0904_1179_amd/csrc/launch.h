@@ -5,15 +5,9 @@
 #include <stdint.h>
 
 #include "device.h"
+#include "layout.h"
 
 namespace su3hb {
-
-constexpr int kBlock = 256;          // threads per workgroup (4 waves of 64)
-constexpr int kPassBlock = 64;       // threads per workgroup of the unmeasured single-torus passes (one wave)
-constexpr int kPlaqBlocksMax = 4096; // workgroups per layer of the plaquette reduction
-constexpr int kCounterSlots = 4096;  // heat-bath counter slots (pairs of u64: attempts, accepts)
-
-int plaq_blocks(const Geom &g);
 
 // One job of a batched pass (continuous batching of several lattices).
 struct BatchJob {
@@ -48,10 +42,6 @@ hipError_t launch_plaquette(int precision, const void *links, const Geom &g, dou
 // the wrong layer (2 * kFaceGroups * face_blocks(g) doubles, one group per
 // plane (nu, mu)).  launch_measure_final adds everything up into sums[0]
 // (total) and sums[1 + l] (layer l).
-int meas_block_size(const Geom &g);
-int meas_blocks(const Geom &g);
-constexpr int kFaceGroups = 6;
-int face_blocks(const Geom &g);
 hipError_t launch_update_measured(int precision, void *links, const Geom &g, int mu, double beta, uint64_t sweep,
                                   uint64_t seed, int nhit, unsigned long long *counters, double *meas, hipStream_t s);
 hipError_t launch_plaq_faces(int precision, const void *links, const Geom &g, double *partials, hipStream_t s);
@@ -62,7 +52,6 @@ hipError_t launch_update_twob(int precision, void *links, const Geom &g, int mu,
                               hipStream_t s);
 // Polyakov loops along direction 3: out[2 l], out[2 l + 1] = sums of Re, Im of Tr/3 over the starts in layer l;
 // partials: 2 * nlat * polyakov_blocks(g) doubles
-int polyakov_blocks(const Geom &g);
 hipError_t launch_polyakov(int precision, const void *links, const Geom &g, double *partials, double *out,
                            hipStream_t s);
 hipError_t launch_reunit(int precision, void *links, const Geom &g, hipStream_t s);

@@ -16,6 +16,7 @@
 #include <deque>
 #include <map>
 #include <new>
+#include <string>
 #include <unordered_map>
 #include <vector>
 
@@ -39,6 +40,7 @@ struct Job {
     int sweeps_done = 0;
     double plaq[3] = {0, 0, 0};
     uint64_t att = 0, acc = 0;
+    int64_t bad_links = 0;
     int slot = -1;  // index into the pinned read-back buffers while retiring
 };
 
@@ -64,7 +66,7 @@ struct su3_server {
     bool dirty = true;
     Group groups[kGroups];
     BatchJob *h_table = nullptr;       // pinned, kGroups * max_active entries
-    double *h_sums = nullptr;          // pinned, 3 per retiring job
+    double *h_sums = nullptr;          // pinned, 4 per retiring job
     unsigned long long *h_cnt = nullptr;  // pinned, 2 * kCounterSlots per retiring job
 
     bool alloc(size_t need, size_t *off)
@@ -181,7 +183,7 @@ su3_status su3_server_create(void *d_arena, size_t arena_bytes, int32_t max_acti
     s->stream = (hipStream_t)hip_stream;
     s->free_blocks[table] = (arena_bytes - table) / kAlign * kAlign;
     hipError_t e = hipHostMalloc((void **)&s->h_table, sizeof(BatchJob) * (size_t)kGroups * max_active);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_sums, sizeof(double) * 3 * (size_t)max_active);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_sums, sizeof(double) * 4 * (size_t)max_active);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&s->h_cnt, sizeof(unsigned long long) * 2 * kCounterSlots * (size_t)max_active);
     if (e != hipSuccess) {
@@ -290,7 +292,7 @@ su3_status run_sweeps(su3_server *s, int32_t max_sweeps, int32_t *n_active, int3
             e = launch_plaquette(j.spec.params.precision, s->arena + j.off, j.g, (double *)(scr + kOffPartials),
                                  (double *)(scr + kOffSums), s->stream);
             if (e == hipSuccess)
-                e = hipMemcpyAsync(s->h_sums + 3 * j.slot, scr + kOffSums, sizeof(double) * 3, hipMemcpyDeviceToHost,
+                e = hipMemcpyAsync(s->h_sums + 4 * j.slot, scr + kOffSums, sizeof(double) * 4, hipMemcpyDeviceToHost,
                                    s->stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(s->h_cnt + (size_t)2 * kCounterSlots * j.slot, scr + kOffCounters,
@@ -302,9 +304,10 @@ su3_status run_sweeps(su3_server *s, int32_t max_sweeps, int32_t *n_active, int3
         for (int64_t id : done) {
             Job &j = s->jobs[id];
             const double V = (double)j.g.Vh * 2.0;
-            const double *sums = s->h_sums + 3 * j.slot;
+            const double *sums = s->h_sums + 4 * j.slot;
             j.plaq[0] = sums[0] / (18.0 * V * j.g.nlat);
             for (int l = 0; l < j.g.nlat; ++l) j.plaq[1 + l] = sums[1 + l] / (18.0 * V);
+            j.bad_links = (int64_t)sums[3];
             const unsigned long long *c = s->h_cnt + (size_t)2 * kCounterSlots * j.slot;
             for (int k = 0; k < kCounterSlots; ++k) {
                 j.att += c[2 * k];
@@ -349,6 +352,30 @@ su3_status su3_server_poll(su3_server *s, int64_t job_id, su3_job_result *out)
     for (int k = 0; k < 3; ++k) out->plaquette[k] = j.plaq[k];
     out->kp_attempts = j.att;
     out->kp_accepts = j.acc;
+    out->bad_links = j.bad_links;
+    return SU3_OK;
+}
+
+su3_status su3_server_get_links(su3_server *s, int64_t job_id, double *host, size_t n_doubles)
+{
+    if (!s || !host) return fail(SU3_EINVAL, "server and host must not be NULL");
+    auto it = s->jobs.find(job_id);
+    if (it == s->jobs.end()) return fail(SU3_EINVAL, "unknown job id");
+    const Job &j = it->second;
+    if (j.state != SU3_JOB_ACTIVE) return fail(SU3_ESTATE, "the job's links are on the device only while it is active");
+    const size_t need = (size_t)144 * j.g.Vh * j.g.nlat;
+    if (n_doubles != need) return fail(SU3_EINVAL, "n_doubles must be 72*V*nlat = " + std::to_string(need));
+    std::vector<unsigned char> buf;
+    try {
+        buf.resize(link_bytes_of(&j.spec.params, j.g));
+    } catch (...) {
+        return fail(SU3_EINVAL, "out of host memory for the staging copy");
+    }
+    hipError_t e = hipMemcpyAsync(buf.data(), s->arena + j.off, buf.size(), hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "job link copy");
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "job link copy sync");
+    unpack_links(j.spec.params.precision, j.g, buf.data(), host);
     return SU3_OK;
 }
 

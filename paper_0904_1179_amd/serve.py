@@ -21,7 +21,7 @@ class su3_job(C.Structure):
 
 class su3_job_result(C.Structure):
     _fields_ = [("state", C.c_int32), ("sweeps_done", C.c_int32), ("plaquette", C.c_double * 3),
-                ("kp_attempts", C.c_uint64), ("kp_accepts", C.c_uint64)]
+                ("kp_attempts", C.c_uint64), ("kp_accepts", C.c_uint64), ("bad_links", C.c_int64)]
 
 
 QUEUED, ACTIVE, DONE = 0, 1, 2
@@ -34,6 +34,7 @@ for _name, _res, _args in (
         ("su3_server_step", _st, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         ("su3_server_run", _st, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         ("su3_server_poll", _st, [_vp, C.c_int64, C.POINTER(su3_job_result)]),
+        ("su3_server_get_links", _st, [_vp, C.c_int64, C.POINTER(C.c_double), C.c_size_t]),
         ("su3_server_stats", _st, [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(C.c_uint64)]),
         ("su3_server_destroy", _st, [_vp])):
     _f = getattr(_lib, _name)
@@ -89,7 +90,14 @@ class Server:
         r = su3_job_result()
         _hb._check(_lib.su3_server_poll(self.h, int(jid), C.byref(r)), "su3_server_poll")
         return {"state": r.state, "sweeps_done": r.sweeps_done, "plaquette": list(r.plaquette),
-                "kp_attempts": r.kp_attempts, "kp_accepts": r.kp_accepts}
+                "kp_attempts": r.kp_attempts, "kp_accepts": r.kp_accepts, "bad_links": r.bad_links}
+
+    def get_links(self, jid, n_doubles):
+        """su3_server_get_links: an active job's links, canonical FP64 layout, shape (n_doubles // 18, 18)."""
+        out = np.empty(int(n_doubles), dtype=np.float64)
+        _hb._check(_lib.su3_server_get_links(self.h, int(jid), out.ctypes.data_as(C.POINTER(C.c_double)),
+                                             out.size), "su3_server_get_links")
+        return out.reshape(-1, 18)
 
     def stats(self):
         u, p, s = C.c_size_t(0), C.c_size_t(0), C.c_uint64(0)

@@ -13,7 +13,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsu3hb.so")
 
-SU3_OK, SU3_EINVAL, SU3_ENOSPC, SU3_EDEVICE, SU3_ESTATE = 0, -1, -2, -3, -4
+SU3_OK, SU3_EINVAL, SU3_ENOSPC, SU3_EDEVICE, SU3_ESTATE, SU3_ENUMERIC = 0, -1, -2, -3, -4, -5
 
 
 class SU3Error(RuntimeError):
@@ -219,6 +219,12 @@ class Lattice:
         self.links_buf = torch.empty(link_bytes, dtype=torch.uint8, device="cuda")
         self.scratch_buf = torch.empty(scratch_bytes, dtype=torch.uint8, device="cuda")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        # the buffers come from the current stream's pool but the library works
+        # on self.stream: tell the caching allocator, so that it does not hand
+        # the memory out again while work queued on self.stream may still use it
+        if self.stream != torch.cuda.current_stream():
+            self.links_buf.record_stream(self.stream)
+            self.scratch_buf.record_stream(self.stream)
         self.ctx = su3_create(self.params, self.links_buf.data_ptr(), link_bytes, self.scratch_buf.data_ptr(),
                               scratch_bytes, self.stream.cuda_stream)
 

@@ -20,9 +20,25 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_algorithmic_bytes_per_update():
-    # 8 link reads and 1 write per update, each link as rows 0 and 1 (12 reals)
-    assert bench.bytes_per_update(64) == 9 * 12 * 8 == 864
-    assert bench.bytes_per_update(32) == 432
+    # 8 link reads and 1 write per update of an 18-real SU(3) matrix: 9 x 18 reals
+    assert bench.bytes_per_update(64) == 9 * 18 * 8 == 1296
+    assert bench.bytes_per_update(32) == 648
+    # the bytes this library must move: the same 9 transfers of the stored rows 0 and 1 (12 reals)
+    assert bench.stored_bytes_per_update(64) == 9 * 12 * 8 == 864
+    assert bench.stored_bytes_per_update(32) == 432
+
+
+def test_chain_deviation_onset():
+    p64 = [0.5, 0.5, 0.5, 0.5]
+    d = bench.chain_deviation([0.5, 0.5 * (1 + 2e-6), 0.5 * (1 + 3e-5), 0.5], p64)
+    assert d["onset_sweep"] == 3
+    assert abs(d["max_rel_err_before_onset"] - 2e-6) < 1e-12
+    assert bench.chain_deviation(p64, p64)["onset_sweep"] is None
+
+
+def test_host_cpu_reports_model_and_counts():
+    h = bench.host_cpu()
+    assert h["model"] and h["nproc"] >= 1 and h["omp_threads"] >= 1
 
 
 @pytest.fixture

@@ -339,3 +339,66 @@ def test_dlt_sweep_measure_per_layer_against_oracle(hb, L, flip):
     for k in range(4):
         ref.sweep(1, 5.7)
         assert np.abs(got[k] - ref.plaquette()).max() < 1e-12, (k, got[k], ref.plaquette())
+
+
+# ------------------------------------------- full lattice, as the bench runs --
+
+@pytest.mark.parametrize("L,nlat", [(32, 1), (16, 2)])
+def test_full_lattice_benched_call_against_oracle(hb, L, nlat):
+    """The call the benchmark times (su3_sweep_measure) at the headline size
+    (32^4, FP64, hot start, seed 1, beta 5.7) and on the 2 x 16^4
+    double-layered torus: every link after sweeps 1 and 2 against the oracle
+    <= 1e-12, the counters exactly, each fused plaquette <= 1e-13; a single
+    two-sweep call ends bit-identical."""
+    _say(f"full-lattice benched call L={L} nlat={nlat}")
+    lat = hb.Lattice(L, nlat=nlat, seed=1)
+    ref = _oracle(L, nlat, seed=1)
+    lat.start(True)
+    ref.start(True)
+    for s in range(2):
+        fused = lat.sweep_measure(1, 5.7)[0]
+        ref.sweep(1, 5.7)
+        got = lat.get_links()
+        dlink = np.abs(got - ref.links()).max()
+        _say(f"  sweep {s + 1}: max |dU| = {dlink:.3e}, fused plaquette {fused}")
+        assert dlink < 1e-12, f"sweep {s + 1}: max |dU| = {dlink:.3e}"
+        assert np.abs(fused - ref.plaquette()).max() <= 1e-13
+        assert lat.counters()[1:] == ref.counters()
+        del got
+    two = hb.Lattice(L, nlat=nlat, seed=1)
+    two.start(True)
+    both = two.sweep_measure(2, 5.7)
+    assert np.array_equal(two.get_links(), lat.get_links())
+    assert np.abs(both[1] - ref.plaquette()).max() <= 1e-13
+
+
+# ----------------------------------------------------- failure detection --
+
+@pytest.mark.parametrize("precision,scale", [(64, 1.0 + 1e-6), (32, 1.0 + 1e-3)])
+def test_non_finite_and_non_unitary_links_are_reported(hb, precision, scale):
+    """A NaN entry or a row off the unit sphere (data loaded through
+    su3_set_links, not a device fault) makes su3_plaquette return
+    SU3_ENUMERIC with the count of bad links; su3_sweep_measure reports a
+    non-finite plaquette the same way; healthy links are accepted again."""
+    lat = hb.Lattice((4, 4, 4, 6), nlat=2, precision=precision, seed=3)
+    lat.start(True)
+    lat.sweep(1, 5.7)
+    good = lat.get_links()
+    lat.plaquette()  # healthy: SU3_OK
+    nan = good.copy()
+    nan[17, 3] = np.nan
+    lat.set_links(nan)
+    with pytest.raises(hb.SU3Error) as e:
+        lat.plaquette()
+    assert e.value.status == hb.su3hb.SU3_ENUMERIC and "1 links" in str(e.value)
+    with pytest.raises(hb.SU3Error) as e:
+        lat.sweep_measure(1, 5.7)
+    assert e.value.status == hb.su3hb.SU3_ENUMERIC
+    off = good.copy()
+    off[[5, 600], 0:6] *= scale  # row 0 of two links scaled off the unit sphere
+    lat.set_links(off)
+    with pytest.raises(hb.SU3Error) as e:
+        lat.plaquette()
+    assert e.value.status == hb.su3hb.SU3_ENUMERIC and "2 links" in str(e.value)
+    lat.set_links(good)
+    lat.plaquette()

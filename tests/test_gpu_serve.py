@@ -131,3 +131,114 @@ def test_short_realtime_stream(hb):
     j = jobs[5]
     p_alone, cnt = _alone(hb, j["L"], 1, 32, j["beta"], j["nsweeps"], j["seed"], 1, 1)
     assert recs[5]["plaquette"][0] == p_alone[0]
+
+
+# ----------------------------------------------------- served jobs vs oracle --
+
+ORACLE_MIX = [
+    # (L, nlat, flip, precision, beta, nsweeps, seed, hot, nhit)
+    (8, 1, None, 64, 5.7, 4, 31, 1, 1),             # periodic, hot
+    (6, 1, None, 64, 6.1, 3, 32, 0, 1),             # periodic, cold
+    ((4, 4, 4, 6), 2, 0x7, 64, 5.7, 4, 33, 1, 1),   # double-layered torus, flips 0x7
+    ((4, 6, 4, 4), 1, None, 64, 5.8, 3, 34, 1, 2),  # two attempts per subgroup
+    ((6, 4, 10, 2), 1, None, 64, 5.9, 3, 35, 1, 1), # ragged: 240 links per pass
+    ((4, 4, 6, 4), 2, 0xF, 64, 5.6, 3, 36, 0, 1),   # double-layered torus, all flips, cold
+    (8, 1, None, 32, 5.7, 3, 37, 1, 1),             # FP32 periodic
+    ((4, 4, 4, 8), 2, 0x7, 32, 5.7, 3, 38, 1, 1),   # FP32 double-layered torus
+]
+
+
+def _job_dicts(mix):
+    return [{"id": k, "arrival": 0.0, "L": L, "nlat": nlat, "flip_mask": flip, "precision": prec, "beta": beta,
+             "nsweeps": nsw, "seed": seed, "hot": hot, "nhit": nhit}
+            for k, (L, nlat, flip, prec, beta, nsw, seed, hot, nhit) in enumerate(mix)]
+
+
+def _oracle_for(spec):
+    from oracle import su3ref
+
+    L, nlat, flip, prec, beta, nsw, seed, hot, nhit = spec
+    o = su3ref.Oracle(L, nlat=nlat, flip_mask=flip, nhit=nhit, seed=seed)
+    o.start(hot)
+    return o
+
+
+def _n_doubles(L, nlat):
+    V = L ** 4 if isinstance(L, int) else int(np.prod(L))
+    return 72 * V * nlat
+
+
+def test_served_jobs_match_oracle_sweep_by_sweep(hb):
+    """Every job of a mixed batch (both precisions, single and double-layered
+    tori, cold and hot, nhit 1 and 2) against the FP64 oracle run on the same
+    spec.  While a job is active its links are read back after every batched
+    sweep: FP64 jobs <= 1e-12 per element, FP32 jobs at FP32 rounding (median
+    <= 1e-5).  At retirement: FP64 per-layer plaquette <= 1e-12 and heat-bath
+    counters exact; FP32 per-layer plaquette relative error <= 1e-5 and exact
+    attempt count."""
+    from paper_0904_1179_amd import serve
+
+    srv = serve.Server(arena_bytes=64 << 20, max_active=16)
+    ids = [srv.submit(serve.make_job(L, beta, nsw, seed, prec, nlat, flip, nhit, hot))
+           for (L, nlat, flip, prec, beta, nsw, seed, hot, nhit) in ORACLE_MIX]
+    refs = [_oracle_for(spec) for spec in ORACLE_MIX]
+    done = set()
+    for step in range(1, max(s[5] for s in ORACLE_MIX) + 1):
+        srv.step()
+        for k, spec in enumerate(ORACLE_MIX):
+            if k in done:
+                continue
+            L, nlat, flip, prec, beta, nsw, seed, hot, nhit = spec
+            refs[k].sweep(1, beta)
+            r = srv.poll(ids[k])
+            if r["state"] == serve.ACTIVE:
+                got = srv.get_links(ids[k], _n_doubles(L, nlat))
+                dev = np.abs(got - refs[k].links()).max(axis=1)
+                _say(f"job {k} {spec[:4]} step {step}: max link dev {dev.max():.2e}")
+                if prec == 64:
+                    assert dev.max() < 1e-12, (k, step, dev.max())
+                else:
+                    assert np.median(dev) < 1e-5, (k, step, np.median(dev))
+                continue
+            assert r["state"] == serve.DONE and r["sweeps_done"] == nsw == step
+            assert r["bad_links"] == 0
+            p = np.array(r["plaquette"][:1 + nlat])
+            pref = refs[k].plaquette()
+            att, acc = refs[k].counters()
+            _say(f"job {k} {spec[:4]} done: plaquette {p}, oracle {pref}")
+            if prec == 64:
+                assert np.abs(p - pref).max() <= 1e-12, (k, p, pref)
+                assert (r["kp_attempts"], r["kp_accepts"]) == (att, acc)
+            else:
+                assert (np.abs(p - pref) / np.abs(pref)).max() <= 1e-5, (k, p, pref)
+                assert r["kp_attempts"] == att
+            done.add(k)
+    assert done == set(range(len(ORACLE_MIX)))
+    with pytest.raises(hb.SU3Error) as e:
+        srv.get_links(ids[0], _n_doubles(8, 1))  # retired: its links are gone
+    assert e.value.status == -4
+
+
+def test_served_jobs_match_oracle_with_admission_waits(hb):
+    """The same mix through an arena that holds about two of these lattices at
+    a time, several sweeps per server call: jobs are admitted late, at other
+    global steps, and their final results still equal the oracle's."""
+    from paper_0904_1179_amd import serve
+
+    p = hb.make_params((4, 4, 4, 8), nlat=2, precision=64)
+    nl, ns = hb.su3_footprint(p)
+    arena = 2 * (nl + ns) + (2 << 20)
+    recs, summary = serve.run_stream(_job_dicts(ORACLE_MIX), arena_bytes=arena, max_active=3, realtime=False,
+                                     sweeps_per_call=8)
+    _say(f"admission-limited mix: {summary['steps']} steps, arena peak {summary['arena_peak_bytes']} of {arena}")
+    for k, spec in enumerate(ORACLE_MIX):
+        L, nlat, flip, prec, beta, nsw, seed, hot, nhit = spec
+        ref = _oracle_for(spec)
+        ref.sweep(nsw, beta)
+        pref = ref.plaquette()
+        pgot = np.array(recs[k]["plaquette"][:1 + nlat])
+        if prec == 64:
+            assert np.abs(pgot - pref).max() <= 1e-12, (k, pgot, pref)
+            assert (recs[k]["kp_attempts"], recs[k]["kp_accepts"]) == ref.counters()
+        else:
+            assert (np.abs(pgot - pref) / np.abs(pref)).max() <= 1e-5, (k, pgot, pref)
