@@ -157,6 +157,26 @@ su3_status su3_polyakov(su3_ctx *c, double *out, int32_t n);
  * Synchronises the stream. */
 su3_status su3_plaquette(su3_ctx *c, double *out, int32_t n);
 
+/* For callers that cannot allocate device memory or synchronise -- code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc --
+ * the plaquette of su3_plaquette without a context or a workspace: the links
+ * in d_links (the tiled layout a context with parameters p keeps, link_bytes
+ * >= su3_footprint's link bytes, 256-byte aligned) are summed with the same
+ * kernels and reduction order, and the results are written to the device
+ * buffer d_out (n_out >= 2 + nlat doubles): d_out[0] the mean plaquette,
+ * d_out[1..nlat] per layer, d_out[1 + nlat] the number of links failing the
+ * check of su3_plaquette (as a double).  Enqueued on hip_stream; nothing is
+ * allocated (no hipMalloc, hipFree or allocating library call) and nothing
+ * waits.  The partial sums live in a library-owned device array of 256 KiB
+ * per GPU (held until the process ends; the largest lattice needs 128 KiB):
+ * every call on a GPU shares it, so calls that overlap on one GPU race, and
+ * the caller must order them (one stream, or events).  Every call overwrites
+ * all of the array it reads, so nothing needs clearing between calls.
+ * SU3_EINVAL / SU3_ENOSPC for invalid parameters, pointers or sizes (checked
+ * before any HIP call), SU3_EDEVICE for a launch failure. */
+su3_status su3_plaquette_noalloc(const su3_params *p, const void *d_links, size_t link_bytes, double *d_out,
+                                 int32_t n_out, void *hip_stream);
+
 /* Project every link back onto SU(3) (Gram-Schmidt of rows 0 and 1, row 2 =
  * conj(row0 x row1)), in FP64 for both precisions.  Not described in the
  * paper, which stores 18 reals per link (App. A, eq. (4)) without saying how

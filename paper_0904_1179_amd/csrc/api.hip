@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -326,6 +327,72 @@ su3_status su3_plaquette(su3_ctx *c, double *out, int32_t n)
                                       " links are not finite or have rows 0, 1 that are not orthonormal within " +
                                       std::to_string(unitarity_tol(c->p.precision)) + "; plaquette " +
                                       std::to_string(out[0]));
+    return SU3_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Workspace of su3_plaquette_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never uses the array's name
+// as an address (on the host it is only a handle for the symbol lookup); the
+// device address comes from hipGetSymbolAddress, once per device, and is
+// kept per device.
+constexpr size_t kNoallocScratchBytes = 256 << 10;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch` (looked up on its first use there).
+su3_status noalloc_scratch(unsigned char **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(SU3_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(SU3_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = (unsigned char *)g_scratch_ptr[dev];
+    return SU3_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+su3_status su3_plaquette_noalloc(const su3_params *p, const void *d_links, size_t link_bytes, double *d_out,
+                                 int32_t n_out, void *hip_stream)
+{
+    su3_status st = check_params(p);
+    if (st != SU3_OK) return st;
+    if (!d_links || !d_out) return fail(SU3_EINVAL, "d_links and d_out must not be NULL");
+    if ((uintptr_t)d_links & 255u) return fail(SU3_EINVAL, "d_links must be 256-byte aligned");
+    if (n_out < 2 + p->nlat) return fail(SU3_EINVAL, "d_out must hold 2 + nlat doubles");
+    const Geom g = make_geom(p);
+    if (link_bytes < link_bytes_of(p, g))
+        return fail(SU3_ENOSPC, "link buffer has " + std::to_string(link_bytes) + " bytes, needs " +
+                                    std::to_string(link_bytes_of(p, g)));
+    // partial sums, then the 4 sums (the same layout as a context's scratch from kOffSums on)
+    const size_t partial_bytes = 2 * sizeof(double) * (size_t)p->nlat * (size_t)plaq_blocks(g);
+    const size_t need = 256 + partial_bytes;
+    if (need > kNoallocScratchBytes)
+        return fail(SU3_EINVAL, "lattice needs " + std::to_string(need) + " bytes of workspace, more than the " +
+                                    std::to_string(kNoallocScratchBytes) + " of su3_plaquette_noalloc");
+    unsigned char *ws = nullptr;
+    st = noalloc_scratch(&ws);
+    if (st != SU3_OK) return st;
+    hipError_t e = su3hb::launch_plaquette(p->precision, d_links, g, (double *)(ws + 256), (double *)ws,
+                                           (hipStream_t)hip_stream, d_out);
+    if (e != hipSuccess) return hip_fail(e, "plaquette kernels");
     return SU3_OK;
 }
 

@@ -845,9 +845,12 @@ __global__ __launch_bounds__(kBlock) void k_measure_final_dlt(const double *__re
 }
 
 // sums[1 + l] = sum over the partials of layer l; sums[0] = sum over layers;
-// sums[3] = number of links that failed the unitarity check
+// sums[3] = number of links that failed the unitarity check.  With `mean`
+// non-null also the normalised values: mean[0] = sums[0] / (norm nlat),
+// mean[1 + l] = sums[1 + l] / norm, mean[1 + nlat] = sums[3] (norm = 18 V).
 __global__ __launch_bounds__(kBlock) void k_plaq_final(const double *__restrict__ partials, int nblk, int nlat,
-                                                       double *__restrict__ sums)
+                                                       double *__restrict__ sums, double *__restrict__ mean,
+                                                       double norm)
 {
     double tot = 0.0;
     for (int l = 0; l < nlat; ++l) {
@@ -867,6 +870,11 @@ __global__ __launch_bounds__(kBlock) void k_plaq_final(const double *__restrict_
         sums[0] = tot;
         if (nlat == 1) sums[2] = 0.0;
         sums[3] = r;
+        if (mean) {
+            mean[0] = tot / (norm * nlat);
+            for (int l = 0; l < nlat; ++l) mean[1 + l] = sums[1 + l] / norm;
+            mean[1 + nlat] = r;
+        }
     }
 }
 
@@ -1068,7 +1076,7 @@ hipError_t launch_measure_final(const double *meas, const double *faces, const G
 }
 
 hipError_t launch_plaquette(int precision, const void *links, const Geom &g, double *partials, double *sums,
-                            hipStream_t s)
+                            hipStream_t s, double *mean)
 {
     const int nblk = plaq_blocks(g);
     const long long tiles = ((long long)g.Vh + kBlock - 1) / kBlock;
@@ -1087,7 +1095,7 @@ hipError_t launch_plaquette(int precision, const void *links, const Geom &g, dou
         else
             k_plaq_partial<float, false><<<grid, kBlock, 0, s>>>((const float2 *)links, g, tpb, tol, partials);
     }
-    k_plaq_final<<<1, kBlock, 0, s>>>(partials, nblk, g.nlat, sums);
+    k_plaq_final<<<1, kBlock, 0, s>>>(partials, nblk, g.nlat, sums, mean, 36.0 * (double)g.Vh);
     return hipGetLastError();
 }
 

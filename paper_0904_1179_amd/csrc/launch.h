@@ -30,8 +30,12 @@ hipError_t launch_update(int precision, void *links, const Geom &g, int mu, int 
 // a double-layered torus (else every job is a single torus)
 hipError_t launch_update_batch(int precision, bool hit1, bool dlt, const BatchJob *d_jobs, int njobs, int ntiles,
                                long long step, int mu, int par, hipStream_t s);
+// Plaquette sums of the whole lattice into sums[0..3] (total, per layer,
+// number of links failing the unitarity check); partials: 2 * nlat *
+// plaq_blocks(g) doubles.  With `mean` non-null also the normalised values
+// mean[0..nlat] and the failing-link count mean[1 + nlat], on the device.
 hipError_t launch_plaquette(int precision, const void *links, const Geom &g, double *partials, double *sums,
-                            hipStream_t s);
+                            hipStream_t s, double *mean = nullptr);
 // The odd pass of mu (1, 2 or 3) that also stores, per workgroup, the sum of
 // its final plaquettes in the planes (nu, mu), nu < mu: meas[b] on a single
 // torus, meas[2 b + layer of the updated site] on a double-layered torus, b <

@@ -47,6 +47,7 @@ def _load():
         "su3_sweep_measure": (st, [vp, C.c_int32, C.c_double, dp, sz]),
         "su3_sweep_betas": (st, [vp, C.c_int32, C.c_double, C.c_double]),
         "su3_polyakov": (st, [vp, dp, C.c_int32]),
+        "su3_plaquette_noalloc": (st, [P, vp, sz, vp, C.c_int32, vp]),
         "su3_reunitarise": (st, [vp]),
         "su3_get_links": (st, [vp, dp, sz]),
         "su3_set_links": (st, [vp, dp, sz]),
@@ -137,6 +138,12 @@ def su3_plaquette(ctx, nlat):
     out = np.zeros(1 + nlat)
     _check(_lib.su3_plaquette(ctx, out.ctypes.data_as(C.POINTER(C.c_double)), 1 + nlat), "su3_plaquette")
     return out
+
+
+def su3_plaquette_noalloc(params, d_links, link_bytes, d_out, n_out, stream):
+    """Asynchronous; writes 2 + nlat doubles to the device buffer d_out."""
+    _check(_lib.su3_plaquette_noalloc(C.byref(params), C.c_void_p(d_links), link_bytes, C.c_void_p(d_out),
+                                      int(n_out), C.c_void_p(stream)), "su3_plaquette_noalloc")
 
 
 def su3_reunitarise(ctx):
