@@ -52,10 +52,11 @@ def stored_bytes_per_update(precision):
 
 
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-# what the pass kernel's counters depend on: its code, its launch shape and the
-# pass order the host picks
+# what the pass kernel's counters depend on: its code, its launch shape, the
+# pass order the host picks and the compiler flags
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0904_1179_amd", "csrc", f)
-                  for f in ("kernels.hip", "device.h", "launch.h", "api.hip")]
+                  for f in ("kernels.hip", "device.h", "geom.h", "launch.h", "layout.cpp", "api.hip")] + \
+                 [os.path.join(ROOT, "paper_0904_1179_amd", "build.py")]
 
 
 def kernel_source_hash():
@@ -135,6 +136,30 @@ def repeat_rates(lat, beta, repeats=10, sweeps=10):
     return {"repeats": repeats, "sweeps_each": sweeps, "median": float(np.median(r)),
             "p10": float(np.percentile(r, 10)), "p90": float(np.percentile(r, 90)), "unit": "link updates/s",
             "timing": "HIP events around su3_sweep on the lattice's stream, each from a fresh hot start"}
+
+
+def device_warmup(ms, nbytes=256 << 20):
+    """Keep the GPU busy with the plain copy kernel for `ms` milliseconds.  A
+    GPU that was idle runs the first ~30 ms of sustained load up to 20 % slower
+    (power-management ramp; a second lattice allocated later runs at full speed
+    from its first sweep), so this runs before the timed steps.  It is not part
+    of the workload and not in the timed region."""
+    import torch
+
+    from paper_0904_1179_amd import su3_stream_copy
+
+    if ms <= 0:
+        return 0.0
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < ms * 1e-3:
+        for _ in range(4):
+            su3_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream)
+        s.synchronize()
+    del src, dst
+    return (time.perf_counter() - t0) * 1e3
 
 
 def copy_probe_gbs(nbytes=1 << 30, reps=10):
@@ -378,28 +403,28 @@ def startup_trace(L, beta, blocks=20, per_block=10, seed=1):
         samples.append({"error": repr(e)})
 
     def sample():
+        # current clocks as the driver reads them (the metrics table is refreshed too rarely for
+        # the ~30 ms scale of the effect)
         import amdsmi
 
+        kinds = {"gfx_mhz": amdsmi.AmdSmiClkType.GFX, "mem_mhz": amdsmi.AmdSmiClkType.MEM,
+                 "fabric_mhz": amdsmi.AmdSmiClkType.DF, "soc_mhz": amdsmi.AmdSmiClkType.SOC}
         while not stop.is_set():
             t = time.perf_counter()
-            try:
-                m = amdsmi.amdsmi_get_gpu_metrics_info(smi)
-                rec = {"t": t}
-                for k in ("current_gfxclk", "average_gfxclk_frequency", "current_uclk", "current_socket_power",
-                          "average_socket_power", "temperature_hotspot", "temperature_mem"):
-                    v = m.get(k)
-                    if isinstance(v, (int, float)):
-                        rec[k] = v
-                samples.append(rec)
-            except Exception as e:  # noqa: BLE001
-                samples.append({"t": t, "error": repr(e)})
-                return
-            time.sleep(0.002)
+            rec = {"t": t}
+            for k, ct in kinds.items():
+                try:
+                    rec[k] = amdsmi.amdsmi_get_clock_info(smi, ct)["clk"]
+                except Exception as e:  # noqa: BLE001 -- a clock domain may not be readable
+                    rec.setdefault("errors", []).append(f"{k}: {e!r}")
+            samples.append(rec)
+            time.sleep(0.001)
 
     th = None
     if smi is not None:
         th = threading.Thread(target=sample, daemon=True)
         th.start()
+        time.sleep(0.2)  # the idle clocks before the first sweep
 
     def run(lat):
         out = []
@@ -427,19 +452,21 @@ def startup_trace(L, beta, blocks=20, per_block=10, seed=1):
         th.join()
 
     def clocks(t0, t1):
-        sel = [s for s in samples if "t" in s and t0 <= s["t"] <= t1 and "error" not in s]
-        if not sel:
-            return {}
-        keys = set().union(*[s.keys() for s in sel]) - {"t"}
-        return {k: round(sum(s[k] for s in sel if k in s) / len([s for s in sel if k in s]), 1) for k in keys}
+        sel = [s for s in samples if "t" in s and t0 <= s["t"] <= t1]
+        keys = set().union(*[s.keys() for s in sel]) - {"t", "errors"} if sel else set()
+        out = {}
+        for k in keys:
+            vals = [s[k] for s in sel if isinstance(s.get(k), (int, float))]
+            if vals:
+                out[k] = round(sum(vals) / len(vals), 1)
+        return out
 
     def rows(r):
         return [{"ms_per_sweep": round(ms, 4), "t_s": round(ta - t_begin, 3), **clocks(ta, tb)} for ta, tb, ms in r]
 
     return {"lattice": f"{L}^4 FP64 hot start, beta={beta}, su3_sweep in blocks of {per_block} sweeps",
-            "A_first_lattice": rows(ra), "B_second_lattice": rows(rb),
-            "samples": len([s for s in samples if "error" not in s]),
-            "sample_errors": [s["error"] for s in samples if "error" in s][:3]}
+            "idle_before": clocks(0.0, t_begin), "A_first_lattice": rows(ra), "B_second_lattice": rows(rb),
+            "samples": len(samples), "sample_errors": sorted({e for s in samples for e in s.get("errors", [])})[:4]}
 
 
 def main():
@@ -457,6 +484,8 @@ def main():
     ap.add_argument("--no-copy-probe", action="store_true", help="skip the 1 GiB copy bandwidth probe")
     ap.add_argument("--no-serving", action="store_true", help="skip the mixed job stream")
     ap.add_argument("--no-configs", action="store_true", help="skip the other configurations (8^4, 16^4, 2x16^4 DLT, 64^4)")
+    ap.add_argument("--device-warmup-ms", type=float, default=100.0,
+                    help="busy the GPU with the copy kernel this long before the first lattice (power ramp)")
     ap.add_argument("--startup-trace", action="store_true",
                     help="only trace the sweep time from the process's first sweep (two lattices, clocks sampled)")
     args = ap.parse_args()
@@ -474,6 +503,7 @@ def main():
     if args.startup_trace:
         print(json.dumps(startup_trace(L, beta)), flush=True)
         return
+    warmed_ms = device_warmup(args.device_warmup_ms)
     main_run = run_gpu(L, prec, args.steps, args.warmup, beta)
     ups = main_run["updates"] / main_run["seconds"]
     pass_s = main_run["pass_ms"] * 1e-3
@@ -510,6 +540,7 @@ def main():
            "plaquette_last": main_run["plaquette"][-1],
            "plaquette_last_full_kernel": main_run["plaquette_full_kernel"],
            "sweep_rate_spread": spread,
+           "device_warmup_ms": round(warmed_ms, 1),
            "roofline": roofline}
 
     if not args.no_fp32 and prec == 64:

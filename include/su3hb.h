@@ -230,6 +230,18 @@ su3_status su3_gauge_transform(su3_ctx *c, uint64_t gseed);
 su3_status su3_profile(su3_ctx *c, int32_t enable);
 su3_status su3_profile_read(su3_ctx *c, double *total_ms, uint64_t *passes);
 
+/* Lanes per link of the heat-bath passes.  By default (lanes = 0) a pass of
+ * more than 65536 links runs one lane per link; smaller passes, which would
+ * leave most of the GPU idle and take about one link update's latency, run 2
+ * (up to 65536 links) or 4 (up to 16384) lanes per link that share the
+ * staple directions and the random draws of the update (1-hit only).  The
+ * result does not depend on the choice: every variant adds in the same order
+ * and gives the same bits.  lanes = 1, 2 or 4 forces that count (2 and 4 need
+ * nhit = 1, else SU3_EINVAL).  su3_get_lanes_per_link returns the count the
+ * passes use. */
+su3_status su3_set_lanes_per_link(su3_ctx *c, int32_t lanes);
+su3_status su3_get_lanes_per_link(su3_ctx *c, int32_t *lanes);
+
 /* Releases the context (host memory and events); never frees caller memory. */
 su3_status su3_destroy(su3_ctx *c);
 

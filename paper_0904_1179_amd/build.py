@@ -16,7 +16,11 @@ LIB = os.path.join(HERE, "libsu3hb.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "api.hip", "server.hip", "layout.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-COMPILE = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
+# -ffp-contract=on: multiply-adds are fused only within one source expression,
+# never by the backend across statements, so the rounding of a computation does
+# not depend on the code around it: the one-lane, several-lanes-per-link and
+# batched pass kernels round every staple and heat-bath step alike
+COMPILE = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=on",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I" + os.path.join(ROOT, "include")]
 # layout.cpp is plain host C++ (no device code)

@@ -30,6 +30,7 @@ struct su3_ctx {
     bool started;
     uint64_t sweep_index;  // index of the next sweep (keys the random numbers)
     uint64_t sweeps_done;  // since the last start
+    int lanes_requested;   // lanes per link of the passes: 0 = by pass size (lanes_per_link)
     // profiling
     bool profile;
     std::vector<hipEvent_t> ev;  // pairs (start, stop)
@@ -124,6 +125,7 @@ su3_status su3_create(const su3_params *p, void *d_links, size_t link_bytes, voi
     c->sweeps_done = 0;
     c->profile = false;
     c->ev_used = 0;
+    c->lanes_requested = 0;
     *out = c;
     return SU3_OK;
 }
@@ -159,6 +161,7 @@ namespace {
 // nu < mu, in meas[(mu - 1) * nlat * meas_blocks .. mu * nlat * meas_blocks).
 su3_status enqueue_sweeps(su3_ctx *c, int32_t n, double beta, double *meas = nullptr, const double *betas = nullptr)
 {
+    const int lanes = lanes_per_link(c->g, c->p.nhit, c->lanes_requested);
     for (int32_t s = 0; s < n; ++s) {
         for (int mu = 0; mu < 4; ++mu)
             for (int par = 0; par < 2; ++par) {
@@ -181,11 +184,12 @@ su3_status enqueue_sweeps(su3_ctx *c, int32_t n, double beta, double *meas = nul
                                                   c->sweep_index, c->p.seed, c->p.nhit, counters_of(c), c->stream);
                 else if (measured)
                     e = su3hb::launch_update_measured(
-                        c->p.precision, c->links, c->g, mu, beta, c->sweep_index, c->p.seed, c->p.nhit,
-                        counters_of(c), meas + (size_t)(mu - 1) * c->g.nlat * su3hb::meas_blocks(c->g), c->stream);
+                        c->p.precision, c->links, c->g, mu, beta, c->sweep_index, c->p.seed, c->p.nhit, lanes,
+                        counters_of(c), meas + (size_t)(mu - 1) * c->g.nlat * su3hb::meas_blocks(c->g, lanes),
+                        c->stream);
                 else
                     e = su3hb::launch_update(c->p.precision, c->links, c->g, mu, par, beta, c->sweep_index, c->p.seed,
-                                             c->p.nhit, counters_of(c), c->stream);
+                                             c->p.nhit, lanes, counters_of(c), c->stream);
                 if (e != hipSuccess) return hip_fail(e, "update kernel");
                 if (timed) {
                     e = hipEventRecord(c->ev[c->ev_used + 1], c->stream);
@@ -273,15 +277,13 @@ su3_status su3_sweep_measure(su3_ctx *c, int32_t n, double beta, double *out, si
         const int32_t m = std::min<int32_t>(kMeasureChunk, n - done);
         for (int32_t k = 0; k < m; ++k) {
             hipError_t e;
-            // the odd passes of mu = 1, 2, 3 measure all six planes; on a double-layered torus one more
-            // kernel finds the plaquettes they file under the wrong layer; one workgroup adds the partials
+            // the odd passes of mu = 1, 2, 3 measure all six planes (per layer of each plaquette's base
+            // site); one workgroup adds the partials
             double *meas = (double *)(c->scratch + meas_offset(c->g));
-            double *faces = (double *)(c->scratch + faces_offset(c->g));
             st = enqueue_sweeps(c, 1, beta, meas);
             if (st != SU3_OK) return st;
-            e = hipSuccess;
-            if (c->p.nlat == 2) e = launch_plaq_faces(c->p.precision, c->links, c->g, faces, c->stream);
-            if (e == hipSuccess) e = launch_measure_final(meas, faces, c->g, slots + 4 * k, c->stream);
+            e = launch_measure_final(meas, c->g, lanes_per_link(c->g, c->p.nhit, c->lanes_requested),
+                                     slots + 4 * k, c->stream);
             if (e != hipSuccess) return hip_fail(e, "plaquette kernels");
         }
         hipError_t e = hipMemcpyAsync(h.data(), slots, sizeof(double) * 4 * m, hipMemcpyDeviceToHost, c->stream);
@@ -553,6 +555,25 @@ su3_status su3_counters(su3_ctx *c, uint64_t *sweeps, uint64_t *kp_attempts, uin
     if (sweeps) *sweeps = c->sweeps_done;
     if (kp_attempts) *kp_attempts = att;
     if (kp_accepts) *kp_accepts = acc;
+    return SU3_OK;
+}
+
+su3_status su3_set_lanes_per_link(su3_ctx *c, int32_t lanes)
+{
+    su3_status st = check_ctx(c);
+    if (st != SU3_OK) return st;
+    if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4) return fail(SU3_EINVAL, "lanes must be 0, 1, 2 or 4");
+    if (lanes > 1 && c->p.nhit != 1) return fail(SU3_EINVAL, "2 or 4 lanes per link need nhit = 1");
+    c->lanes_requested = lanes;
+    return SU3_OK;
+}
+
+su3_status su3_get_lanes_per_link(su3_ctx *c, int32_t *lanes)
+{
+    su3_status st = check_ctx(c);
+    if (st != SU3_OK) return st;
+    if (!lanes) return fail(SU3_EINVAL, "lanes is NULL");
+    *lanes = lanes_per_link(c->g, c->p.nhit, c->lanes_requested);
     return SU3_OK;
 }
 

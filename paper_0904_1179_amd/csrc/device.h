@@ -38,6 +38,11 @@ template <typename R> __device__ __forceinline__ Cx<R> cmadd_nc(Cx<R> c, Cx<R> a
 {
     return Cx<R>{c.re + a.re * b.re + a.im * b.im, c.im + a.im * b.re - a.re * b.im};
 }
+// conj(a) * b
+template <typename R> __device__ __forceinline__ Cx<R> cmul_cn(Cx<R> a, Cx<R> b)
+{
+    return Cx<R>{a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
 // c + conj(a) * b
 template <typename R> __device__ __forceinline__ Cx<R> cmadd_cn(Cx<R> c, Cx<R> a, Cx<R> b)
 {

@@ -25,43 +25,86 @@ namespace su3hb {
 namespace {
 
 // ---------------------------------------------------------------------------
-// staple: A += U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+ + U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)
-// written as a (c b)^+ + (e d)^+ f with
-//   a = U_nu(x+mu), b = U_mu(x+nu), c = U_nu(x), d = U_nu(x+mu-nu), e = U_mu(x-nu), f = U_nu(x-nu)
-// b and e come from the caller (see update_link); the pairs (c, d) and (a, f)
-// are loaded together: c of thread x is d of thread x + nu - mu, a of thread
-// x is f of thread x + mu + nu.
+// Staple of U_MU(x): A = sum over nu != MU (ascending) of D_nu,
+//   D_nu = up_nu + dn_nu,
+//   up_nu = U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+ = a (c b)^+,
+//   dn_nu = U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu) = (e d)^+ f,
+// with a = U_nu(x+mu), b = U_mu(x+nu), c = U_nu(x), d = U_nu(x+mu-nu),
+// e = U_mu(x-nu), f = U_nu(x-nu).  up_nu is the plaquette based at x, dn_nu
+// the one based at x - nu.
+//
+// Rounding order, fixed for every kernel: c b, e d and a (c b)^+ are SU(3)
+// products (rows 0 and 1 formed, row 2 rebuilt); dn_nu is formed entry by
+// entry from zero; D_nu = up_nu + dn_nu entry by entry; A = (D_0 + D_1) + D_2
+// over the three directions in increasing order.  The one-lane pass, the
+// several-lanes-per-link pass and the batched server pass all add in exactly
+// this order, so a lattice gets the same bits from each of them.
 // ---------------------------------------------------------------------------
-// TWOB (double-layered torus with per-layer couplings wb[0], wb[1]): the upper
-// term belongs to the plaquette based at x, the lower one to the plaquette
-// based at x - nu; each is weighted by the coupling of that base site's layer.
-template <int MU, int NU, typename R, bool DLT, bool TWOB = false>
-__device__ __forceinline__ void add_staple(M3<R> &A, const M3<R> &b, const M3<R> &e,
+
+// D = a (c b)^+ + (e d)^+ f from cb = c b and ed = e d.  CROSS: also
+// cross += (e d)^+ f when `crosses` (the lower plaquette's base site lies in
+// the other layer of a double-layered torus).
+template <typename R, bool CROSS>
+__device__ __forceinline__ void staple_term(M3<R> &D, const M3<R> &a, const M3<R> &cb, const M3<R> &ed,
+                                            const M3<R> &f, M3<R> &cross, bool crosses)
+{
+    D = mul_nd_su3(a, cb);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Cx<R> dn = cmul_cn(ed.e[0][r], f.e[0][c]);
+            dn = cmadd_cn(dn, ed.e[1][r], f.e[1][c]);
+            dn = cmadd_cn(dn, ed.e[2][r], f.e[2][c]);
+            D.e[r][c].re += dn.re;
+            D.e[r][c].im += dn.im;
+            if constexpr (CROSS) {
+                cross.e[r][c].re += crosses ? dn.re : R(0);
+                cross.e[r][c].im += crosses ? dn.im : R(0);
+            }
+        }
+}
+
+// D_NU of the one-lane pass; b = U_MU(x+NU) and e = U_MU(x-NU) come from the
+// caller.  The pairs (c, d) and (a, f) are loaded together: c of thread x is d
+// of thread x + NU - MU, a of thread x is f of thread x + MU + NU.
+template <int MU, int NU, typename R, bool DLT, bool CROSS>
+__device__ __forceinline__ void staple_dir(M3<R> &D, const M3<R> &b, const M3<R> &e,
                                            const store_t<R> *__restrict__ links, const Geom &g, const int x[4],
-                                           int layer, int par, int n, const R *wb = nullptr)
+                                           int layer, int par, int n, M3<R> &cross, bool take_cross = true)
 {
     const int opp = par ^ 1;
     M3<R> c, d, a, f;
     load_link12_pair<R>(c, planes<R>(links, g, NU, par), n, d, planes<R>(links, g, NU, par),
                         nbr_elem<MU, +1, NU, -1, DLT>(g, x, layer));
-    // c b, e d and a (c b)^+ are SU(3) products: rows 0 and 1 formed, row 2
-    // rebuilt (so the third rows of c, e and a are never needed)
     const M3<R> cb = mul_nn_su3(c, b);
     const M3<R> ed = mul_nn_su3(e, d);
-    const int elo = nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer);
     load_link12_pair<R>(a, planes<R>(links, g, NU, opp), nbr_elem<MU, +1, NU, 0, DLT>(g, x, layer), f,
+                        planes<R>(links, g, NU, opp), nbr_elem<NU, -1, MU, 0, DLT>(g, x, layer));
+    staple_term<R, CROSS>(D, a, cb, ed, f, cross, CROSS && take_cross && x[NU] == 0 && ((g.flip >> NU) & 1u));
+}
+
+// Per-layer couplings (double-layered torus): A += w(x) up_nu + w(x - nu) dn_nu,
+// w = the coupling of the base site's layer.
+template <int MU, int NU, typename R>
+__device__ __forceinline__ void add_staple_twob(M3<R> &A, const M3<R> &b, const M3<R> &e,
+                                                const store_t<R> *__restrict__ links, const Geom &g, const int x[4],
+                                                int layer, int par, int n, const R *wb)
+{
+    const int opp = par ^ 1;
+    M3<R> c, d, a, f;
+    load_link12_pair<R>(c, planes<R>(links, g, NU, par), n, d, planes<R>(links, g, NU, par),
+                        nbr_elem<MU, +1, NU, -1, true>(g, x, layer));
+    const M3<R> cb = mul_nn_su3(c, b);
+    const M3<R> ed = mul_nn_su3(e, d);
+    const int elo = nbr_elem<NU, -1, MU, 0, true>(g, x, layer);
+    load_link12_pair<R>(a, planes<R>(links, g, NU, opp), nbr_elem<MU, +1, NU, 0, true>(g, x, layer), f,
                         planes<R>(links, g, NU, opp), elo);
-    const M3<R> up = mul_nd_su3(a, cb);
-    if constexpr (TWOB) {
-        scale_acc(A, up, wb[layer]);
-        M3<R> t;
-        set_zero(t);
-        acc_dn(t, ed, f);
-        scale_acc(A, t, wb[elo >= g.Vh ? 1 : 0]);
-    } else {
-        add_to(A, up);
-        acc_dn(A, ed, f);
-    }
+    scale_acc(A, mul_nd_su3(a, cb), wb[layer]);
+    M3<R> t;
+    set_zero(t);
+    acc_dn(t, ed, f);
+    scale_acc(A, t, wb[elo >= g.Vh ? 1 : 0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -77,12 +120,49 @@ __device__ __forceinline__ void add_staple(M3<R> &A, const M3<R> &b, const M3<R>
 // accept decisions in FP64); the uniforms are formed exactly in FP64 first.
 // The link is reunitarised in FP64 at the end.
 // ---------------------------------------------------------------------------
-// Returns Re Tr W after the last subgroup, i.e. Re Tr(U_new A) before the
-// final reunitarisation: the sum of the six plaquettes through the new link.
-template <typename R, bool HIT1>
-__device__ __forceinline__ double heatbath(M3<R> &U, const M3<R> &A, double beta_d, uint64_t seed, uint64_t lid,
-                                           uint64_t sweep, int nhit, int &att, int &acc)
+
+// What an attempt needs from its random numbers, independent of the link:
+// q = ln u1 + cos^2(2 pi u2) ln u3 (so lambda^2 = -q / (2 alpha)), u4^2,
+// cos(theta), sin(theta) cos(phi), sin(theta) sin(phi).  Several lanes of one
+// link compute the three subgroups' draws at once and exchange them; the
+// one-lane pass computes each where it is used.  Both produce the same values.
+template <typename R> struct KPDraw {
+    R q, u4sq, cth, sc, ss;
+};
+
+template <typename R>
+__device__ __forceinline__ KPDraw<R> kp_draw(uint64_t seed, uint64_t lid, uint64_t sweep, int sub, int t)
 {
+    const U64x4 w = philox4x64_10(lid, sweep, ((uint64_t)sub << 32) | (uint64_t)t, kTagHeatbath, seed, 0);
+    const R u1 = R(unif52(w.w[0]));
+    const R u3 = R(unif52(w.w[1]));
+    const R u2 = R(unif32((uint32_t)w.w[2]));
+    const R u4 = R(unif32((uint32_t)(w.w[2] >> 32)));
+    const R u5 = R(unif32((uint32_t)w.w[3]));
+    const R u6 = R(unif32((uint32_t)(w.w[3] >> 32)));
+    KPDraw<R> d;
+    const R c2 = cospi_sq_r(R(2) * u2);
+    d.q = log_r(u1) + c2 * log_r(u3);
+    d.u4sq = u4 * u4;
+    d.cth = R(2) * u5 - R(1);
+    // FP64: |cth| < 1 (u5 is never 0 or 1), so the argument is positive
+    const R sth = sqrt_pos_r(R(1) - d.cth * d.cth);
+    R sph, cph;
+    sincospi_r(R(2) * u6, &sph, &cph);
+    d.sc = sth * cph;
+    d.ss = sth * sph;
+    return d;
+}
+
+// PRE: the draws of attempt 0 of the three subgroups are given in pre[0..2]
+// (1-hit only).  Returns Re Tr W after the last subgroup, i.e. Re Tr(U_new A)
+// before the final reunitarisation.
+template <typename R, bool HIT1, bool PRE = false>
+__device__ __forceinline__ double heatbath(M3<R> &U, const M3<R> &A, double beta_d, uint64_t seed, uint64_t lid,
+                                           uint64_t sweep, int nhit, int &att, int &acc,
+                                           const KPDraw<R> *pre = nullptr)
+{
+    static_assert(!PRE || HIT1, "given draws: one attempt per subgroup");
     if (HIT1) nhit = 1;  // 1-hit: a single attempt, no loop
     // 1/(2 alpha) = 3/(4 beta k): one division per link and 1/k per subgroup
     const R q34b = R(0.75) / R(beta_d);
@@ -102,28 +182,20 @@ __device__ __forceinline__ double heatbath(M3<R> &U, const M3<R> &A, double beta
         bool ok = false;
         R a0 = R(1), a1 = R(0), a2 = R(0), a3 = R(0);
         for (int t = 0; t < (HIT1 ? 1 : nhit); ++t) {
-            const U64x4 w = philox4x64_10(lid, sweep, ((uint64_t)sub << 32) | (uint64_t)t, kTagHeatbath, seed, 0);
+            KPDraw<R> d;
+            if constexpr (PRE)
+                d = pre[sub];
+            else
+                d = kp_draw<R>(seed, lid, sweep, sub, t);
             ++att;
-            const R u1 = R(unif52(w.w[0]));
-            const R u3 = R(unif52(w.w[1]));
-            const R u2 = R(unif32((uint32_t)w.w[2]));
-            const R u4 = R(unif32((uint32_t)(w.w[2] >> 32)));
-            const R c2 = cospi_sq_r(R(2) * u2);
-            const R lam2 = -(log_r(u1) + c2 * log_r(u3)) * inv2alpha;
-            if (u4 * u4 <= R(1) - lam2) {
-                const R u5 = R(unif32((uint32_t)w.w[3]));
-                const R u6 = R(unif32((uint32_t)(w.w[3] >> 32)));
+            const R lam2 = -d.q * inv2alpha;
+            if (d.u4sq <= R(1) - lam2) {
                 a0 = R(1) - R(2) * lam2;
-                const R cth = R(2) * u5 - R(1);
-                // FP64: |cth| < 1 (u5 is never 0 or 1), so the argument is positive
-                const R sth = sqrt_pos_r(R(1) - cth * cth);
-                R sph, cph;
-                sincospi_r(R(2) * u6, &sph, &cph);
                 const R rho2 = R(1) - a0 * a0;
                 const R rho = rho2 > R(0) ? sqrt_pos_r(rho2) : R(0);
-                a1 = rho * sth * cph;
-                a2 = rho * sth * sph;
-                a3 = rho * cth;
+                a1 = rho * d.sc;
+                a2 = rho * d.ss;
+                a3 = rho * d.cth;
                 ok = true;
                 break;
             }
@@ -182,13 +254,16 @@ template <typename R> __device__ __forceinline__ double retr_mul(const M3<R> &u,
 // order is used with STASH (kStashPass, kStashBatch); otherwise b and e are
 // loaded in their direction's phase and `stash` is unused.
 //
-// MEAS: also return Re Tr(U_new S) with S the staple terms of the directions
-// nu < MU.  Summed over the sites of one parity these are all plaquettes of
-// the planes (nu, MU), nu < MU, each once (the upper term of site x is the
-// plaquette based at x, the lower one that based at x - nu).  After the odd
-// pass of MU no later pass of the sweep changes U_nu or U_MU for nu < MU, so
-// the odd passes of MU = 1, 2, 3 together give the final plaquettes of all
-// six planes.  Without MEAS the return value is Re Tr(U_new A) (unused).
+// MEAS: also return tr = Re Tr(U_new S) with S = sum of D_nu over the
+// directions nu < MU.  Summed over the sites of one parity these are all
+// plaquettes of the planes (nu, MU), nu < MU, each once (the upper term of
+// site x is the plaquette based at x, the lower one that based at x - nu).
+// After the odd pass of MU no later pass of the sweep changes U_nu or U_MU for
+// nu < MU, so the odd passes of MU = 1, 2, 3 together give the final
+// plaquettes of all six planes.  On a double-layered torus a lower term whose
+// base x - nu lies in the other layer (x_nu = 0 across a flipped boundary) is
+// also summed separately, trx = Re Tr(U_new S_cross): its plaquette belongs to
+// the other layer.
 constexpr int kStashSlots = 3;
 // Waves per SIMD the pass kernels are compiled for: register budgets of 256
 // (FP64) and 128 (FP32) VGPRs; the stash (3 * 6 * kBlock entries: 72 KiB in
@@ -200,8 +275,40 @@ template <typename R> constexpr int kPassWaves = sizeof(R) == 8 ? 2 : 4;
 // issue at the same rate), so it keeps the direction-by-direction order.  On
 // a double-layered torus the six layer-dependent addresses of MU = 0 at once
 // spill, and so does the batched pass (which also holds its job record).
-template <typename R, bool DLT, int MU> constexpr bool kStashPass = sizeof(R) == 8 && (!DLT || MU > 0);
+// The measured passes of a double-layered torus also hold the cross-layer
+// staple sum and would spill with the stash.
+template <typename R, bool DLT, int MU, bool MEAS = false>
+constexpr bool kStashPass = sizeof(R) == 8 && (!DLT || (MU > 0 && !MEAS));
 template <typename R, bool DLT> constexpr bool kStashBatch = sizeof(R) == 8 && !DLT;
+// FP32 1-hit passes draw the random numbers of the three subgroups right
+// after issuing the first staple loads, so that the Philox and logarithm work
+// fills the wait for them (the draws do not depend on the link): +9 % at
+// 32^4, +7 % at 64^4.  The FP64 pass, whose two waves per SIMD already keep
+// the vector unit busy, lost 1 % with it.
+template <typename R> constexpr bool kEarlyDraws = sizeof(R) == 4;
+// Measured passes of a double-layered torus keep the measured staple sums S
+// and S_cross in LDS across the heat bath (held in registers they spill);
+// these passes run with one wave per SIMD, so the LDS is otherwise unused.
+template <typename R, int NB> __device__ __forceinline__ void park(store_t<R> *buf, int slot, const M3<R> &m)
+{
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        store_t<R> v;
+        v.x = m.e[e / 3][e % 3].re;
+        v.y = m.e[e / 3][e % 3].im;
+        buf[(slot * 9 + e) * NB + threadIdx.x] = v;
+    }
+}
+template <typename R, int NB> __device__ __forceinline__ M3<R> unpark(const store_t<R> *buf, int slot)
+{
+    M3<R> m;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        const store_t<R> v = buf[(slot * 9 + e) * NB + threadIdx.x];
+        m.e[e / 3][e % 3] = Cx<R>{v.x, v.y};
+    }
+    return m;
+}
 template <typename R> struct Raw12 {
     store_t<R> v[6];  // rows 0 and 1 as stored
 };
@@ -233,11 +340,12 @@ __device__ __forceinline__ void stash_fence() { __asm__ __volatile__("" ::: "mem
 
 template <int MU, typename R, bool HIT1, bool DLT, bool TWOB = false, bool MEAS = false, bool STASH = false,
           int NB = kBlock>
-__device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, const Geom &g, int par, int v,
-                                              double beta, uint64_t sweep, uint64_t seed, int nhit, int &att, int &acc,
-                                              store_t<R> *stash, const R *wb = nullptr)
+__device__ __forceinline__ void update_link(store_t<R> *__restrict__ links, const Geom &g, int par, int v, double beta,
+                                            uint64_t sweep, uint64_t seed, int nhit, int &att, int &acc,
+                                            store_t<R> *stash, double &tr, double &trx, const R *wb = nullptr)
 {
     static_assert(!MEAS || (MU > 0 && !TWOB), "measured passes: MU = 1, 2, 3 with one coupling");
+    constexpr bool CROSS = MEAS && DLT;
     // the staple directions nu != MU in increasing order
     constexpr int N0 = MU == 0 ? 1 : 0;
     constexpr int N1 = MU <= 1 ? 2 : 1;
@@ -246,24 +354,45 @@ __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, co
     int x[4];
     const int i = order_site(g, par, v - layer * g.Vh, x);
     const int n = layer * g.Vh + i;
-    M3<R> A, S;
-    set_zero(A);
+    M3<R> A, S, Sx;
+    if constexpr (CROSS) set_zero(Sx);
+    constexpr bool EARLY = kEarlyDraws<R> && HIT1 && !TWOB;
+    const uint64_t site = (uint64_t)layer * (uint64_t)(2 * g.Vh) + (uint64_t)lex_of(g, x);
+    KPDraw<R> pre[3];
     __builtin_amdgcn_s_setprio(1);  // gathering the staple: issue loads ahead of waves in the heat bath
-    if constexpr (!STASH) {
-        // b and e of each direction loaded in its phase
+    if constexpr (TWOB) {
         const store_t<R> *umu = planes<R>(links, g, MU, par ^ 1);
         M3<R> b, e;
+        set_zero(A);
+        load_link12_pair<R>(b, umu, nbr_elem<N0, +1, MU, 0, true>(g, x, layer), e, umu,
+                            nbr_elem<N0, -1, MU, 0, true>(g, x, layer));
+        add_staple_twob<MU, N0, R>(A, b, e, links, g, x, layer, par, n, wb);
+        load_link12_pair<R>(b, umu, nbr_elem<N1, +1, MU, 0, true>(g, x, layer), e, umu,
+                            nbr_elem<N1, -1, MU, 0, true>(g, x, layer));
+        add_staple_twob<MU, N1, R>(A, b, e, links, g, x, layer, par, n, wb);
+        load_link12_pair<R>(b, umu, nbr_elem<N2, +1, MU, 0, true>(g, x, layer), e, umu,
+                            nbr_elem<N2, -1, MU, 0, true>(g, x, layer));
+        add_staple_twob<MU, N2, R>(A, b, e, links, g, x, layer, par, n, wb);
+    } else if constexpr (!STASH) {
+        // b and e of each direction loaded in its phase
+        const store_t<R> *umu = planes<R>(links, g, MU, par ^ 1);
+        M3<R> b, e, T;
         load_link12_pair<R>(b, umu, nbr_elem<N0, +1, MU, 0, DLT>(g, x, layer), e, umu,
                             nbr_elem<N0, -1, MU, 0, DLT>(g, x, layer));
-        add_staple<MU, N0, R, DLT, TWOB>(A, b, e, links, g, x, layer, par, n, wb);
+        if constexpr (EARLY)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) pre[k] = kp_draw<R>(seed, 4 * site + MU, sweep, k, 0);
+        staple_dir<MU, N0, R, DLT, CROSS>(A, b, e, links, g, x, layer, par, n, Sx);
         if constexpr (MEAS && MU == 1) S = A;
         load_link12_pair<R>(b, umu, nbr_elem<N1, +1, MU, 0, DLT>(g, x, layer), e, umu,
                             nbr_elem<N1, -1, MU, 0, DLT>(g, x, layer));
-        add_staple<MU, N1, R, DLT, TWOB>(A, b, e, links, g, x, layer, par, n, wb);
+        staple_dir<MU, N1, R, DLT, CROSS && (N1 < MU)>(T, b, e, links, g, x, layer, par, n, Sx);
+        add_to(A, T);
         if constexpr (MEAS && MU == 2) S = A;
         load_link12_pair<R>(b, umu, nbr_elem<N2, +1, MU, 0, DLT>(g, x, layer), e, umu,
                             nbr_elem<N2, -1, MU, 0, DLT>(g, x, layer));
-        add_staple<MU, N2, R, DLT, TWOB>(A, b, e, links, g, x, layer, par, n, wb);
+        staple_dir<MU, N2, R, DLT, CROSS && (N2 < MU)>(T, b, e, links, g, x, layer, par, n, Sx);
+        add_to(A, T);
     } else {
         Raw12<R> b0, e0, b1, e1, b2, e2;
         {
@@ -284,23 +413,35 @@ __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, co
                 e2.v[e] = pe2[e * kTile];
             }
         }
+        if constexpr (EARLY)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) pre[k] = kp_draw<R>(seed, 4 * site + MU, sweep, k, 0);
         stash_put<R, NB>(stash, 0, b1);
         stash_put<R, NB>(stash, 1, e1);
         stash_put<R, NB>(stash, 2, b2);
         stash_fence();
-        add_staple<MU, N0, R, DLT, TWOB>(A, from_raw(b0), from_raw(e0), links, g, x, layer, par, n, wb);
+        M3<R> T;
+        staple_dir<MU, N0, R, DLT, CROSS>(A, from_raw(b0), from_raw(e0), links, g, x, layer, par, n, Sx);
         if constexpr (MEAS && MU == 1) S = A;
-        add_staple<MU, N1, R, DLT, TWOB>(A, stash_get<R, NB>(stash, 0), stash_get<R, NB>(stash, 1), links, g, x, layer, par,
-                                         n, wb);
+        staple_dir<MU, N1, R, DLT, CROSS && (N1 < MU)>(T, stash_get<R, NB>(stash, 0), stash_get<R, NB>(stash, 1),
+                                                       links, g, x, layer, par, n, Sx);
+        add_to(A, T);
         if constexpr (MEAS && MU == 2) S = A;
-        add_staple<MU, N2, R, DLT, TWOB>(A, stash_get<R, NB>(stash, 2), from_raw(e2), links, g, x, layer, par, n, wb);
+        staple_dir<MU, N2, R, DLT, CROSS && (N2 < MU)>(T, stash_get<R, NB>(stash, 2), from_raw(e2), links, g, x,
+                                                       layer, par, n, Sx);
+        add_to(A, T);
+    }
+    if constexpr (CROSS) {
+        // S and S_cross wait in LDS (`stash`, 2 * 9 * NB entries) across the heat bath
+        if constexpr (MU < 3) park<R, NB>(stash, 0, S);
+        park<R, NB>(stash, 1, Sx);
+        stash_fence();
     }
     store_t<R> *own = planes<R>(links, g, MU, par);
     M3<R> U = load_link12_nt<R>(own, n);
-    const uint64_t site = (uint64_t)layer * (uint64_t)(2 * g.Vh) + (uint64_t)lex_of(g, x);
     // with per-layer couplings the staple carries them: alpha = 2k/3
     __builtin_amdgcn_s_setprio(0);
-    double trw = heatbath<R, HIT1>(U, A, TWOB ? 1.0 : beta, seed, 4 * site + MU, sweep, nhit, att, acc);
+    tr = heatbath<R, HIT1, EARLY>(U, A, TWOB ? 1.0 : beta, seed, 4 * site + MU, sweep, nhit, att, acc, pre);
     // FP64: nontemporal, so the written link does not displace staple links
     // from L2 (a plain store: -3 % at 32^4).  FP32, bound by issue rather
     // than memory: a plain store (+1 %)
@@ -308,8 +449,13 @@ __device__ __forceinline__ double update_link(store_t<R> *__restrict__ links, co
         store_link_nt<R>(own, n, U);
     else
         store_link<R>(own, n, U);
-    if constexpr (MEAS && MU < 3) trw = retr_mul(U, S);
-    return trw;
+    if constexpr (CROSS) {
+        stash_fence();
+        if constexpr (MU < 3) tr = retr_mul(U, unpark<R, NB>(stash, 0));
+        trx = retr_mul(U, unpark<R, NB>(stash, 1));
+    } else if constexpr (MEAS && MU < 3) {
+        tr = retr_mul(U, S);
+    }
 }
 
 // Exact integer heat-bath counts: packed (attempts | accepts << 16) summed
@@ -364,46 +510,62 @@ __device__ __forceinline__ int pass_tile(int par)
     return par ? (int)gridDim.x - 1 - t : t;
 }
 
-// One checkerboard pass in workgroups of NB threads (kBlock, or kPassBlock
-// for the unmeasured passes of a single torus).  MEAS (odd passes of MU = 1,
-// 2, 3; NB = kBlock): also store, per workgroup, the sum over its links of
+// Sum of a per-layer value pair over the workgroup of a measured pass:
+// layer 0 gets s0, layer 1 gets s1 (double-layered torus).
+template <int NB>
+__device__ __forceinline__ void store_meas(double *__restrict__ meas, bool dlt, double s0, double s1)
+{
+    __syncthreads();
+    if (dlt) {
+        const double b0 = block_sum<NB>(s0);
+        __syncthreads();
+        const double b1 = block_sum<NB>(s1);
+        if (threadIdx.x == 0) {
+            meas[2 * blockIdx.x] = b0;
+            meas[2 * blockIdx.x + 1] = b1;
+        }
+    } else {
+        const double b = block_sum<NB>(s0);
+        if (threadIdx.x == 0) meas[blockIdx.x] = b;
+    }
+}
+
+// One checkerboard pass, one lane per link, in workgroups of NB threads
+// (kPassBlock on a single torus, kBlock on a double-layered one).  MEAS (odd
+// passes of MU = 1, 2, 3): also store, per workgroup, the sum over its links of
 // the final plaquettes of the planes (nu, MU), nu < MU, that update_link
-// returns; on a double-layered torus one sum per layer of the updated site.
+// returns; on a double-layered torus one sum per layer, each plaquette filed
+// under its base site's layer.
+// The measured passes of a double-layered torus are compiled for one wave per
+// SIMD (the whole register file; a 2 x 16^4 pass has one wave per SIMD anyway)
+template <typename R, bool DLT, bool MEAS> constexpr int kUpdateWaves = (DLT && MEAS) ? 1 : kPassWaves<R>;
+
 template <int MU, typename R, bool HIT1, bool DLT, bool MEAS = false, int NB = kBlock>
-__global__ __launch_bounds__(NB, kPassWaves<R>) void k_update(store_t<R> *__restrict__ links, const Geom g, const int par,
+__global__ __launch_bounds__(NB, (kUpdateWaves<R, DLT, MEAS>)) void k_update(store_t<R> *__restrict__ links, const Geom g, const int par,
                                                    const double beta, const uint64_t sweep, const uint64_t seed,
                                                    const int nhit, unsigned long long *__restrict__ counters,
                                                    double *__restrict__ meas = nullptr)
 {
-    constexpr bool kStash = kStashPass<R, DLT, MU>;
+    constexpr bool kStash = kStashPass<R, DLT, MU, MEAS>;
     store_t<R> *st = nullptr;
     if constexpr (kStash) {
         __shared__ store_t<R> stash[kStashSlots * 6 * NB];
         st = stash;
+    } else if constexpr (MEAS && DLT) {
+        __shared__ store_t<R> parked[2 * 9 * NB];
+        st = parked;
     }
     const int v = pass_tile(par) * NB + threadIdx.x;
     int att = 0, acc = 0;
-    double trw = 0.0;
+    double tr = 0.0, trx = 0.0;
     if (v < g.nlat * g.Vh)
-        trw = update_link<MU, R, HIT1, DLT, false, MEAS, kStash, NB>(links, g, par, v, beta, sweep, seed, nhit, att, acc,
-                                                                 st);
+        update_link<MU, R, HIT1, DLT, false, MEAS, kStash, NB>(links, g, par, v, beta, sweep, seed, nhit, att, acc,
+                                                               st, tr, trx);
     count_block<NB>(att, acc, counters, blockIdx.x % kCounterSlots);
-    if (MEAS) {
-        __syncthreads();
-        if constexpr (DLT) {
-            // per layer of the updated site: meas[2 b + layer]
-            const bool l1 = v >= g.Vh;
-            const double b0 = block_sum<NB>(l1 ? 0.0 : trw);
-            __syncthreads();
-            const double b1 = block_sum<NB>(l1 ? trw : 0.0);
-            if (threadIdx.x == 0) {
-                meas[2 * blockIdx.x] = b0;
-                meas[2 * blockIdx.x + 1] = b1;
-            }
-        } else {
-            const double b = block_sum<NB>(trw);
-            if (threadIdx.x == 0) meas[blockIdx.x] = b;
-        }
+    if constexpr (MEAS) {
+        // the cross-layer lower plaquettes go to the other layer
+        const bool l1 = DLT && v >= g.Vh;
+        store_meas<NB>(meas, DLT, l1 ? trx : tr - trx, l1 ? tr - trx : trx);
     }
 }
 
@@ -417,9 +579,237 @@ __global__ __launch_bounds__(kBlock, kPassWaves<R>) void k_update_twob(store_t<R
     const int v = pass_tile(par) * kBlock + threadIdx.x;
     const R b[2] = {R(beta0), R(beta1)};
     int att = 0, acc = 0;
+    double tr, trx;
     if (v < g.nlat * g.Vh)
-        update_link<MU, R, HIT1, true, true>(links, g, par, v, 1.0, sweep, seed, nhit, att, acc, nullptr, b);
+        update_link<MU, R, HIT1, true, true>(links, g, par, v, 1.0, sweep, seed, nhit, att, acc, nullptr, tr, trx, b);
     count_block(att, acc, counters, blockIdx.x % kCounterSlots);
+}
+
+// ---------------------------------------------------------------------------
+// Several lanes per link (K = 2 or 4, 1-hit): for passes too small to fill
+// the GPU with one lane per link, where a pass takes about one update's
+// latency.  The K lanes of a link (a quad-aligned group) split the work that
+// does not depend on the link's state: lane q computes the staple part
+// D_{nu_q} of direction nu_q and the random draw of subgroup q, with the same
+// instructions in every lane (the direction is a per-lane value), then the
+// parts are added across the group with DPP quad permutes in the canonical
+// order (D_0 + D_1) + D_2 and every lane runs the heat bath on the full staple.
+//  * K = 4: lanes 0, 1, 2 take directions N0, N1, N2 and subgroups 0, 1, 2;
+//    lane 3 repeats lane 2.  Lanes 2 and 3 each halve D_2 (exact), so the
+//    butterfly xor 1 gives D_0 + D_1 and D_2/2 + D_2/2 = D_2, and xor 2 gives
+//    (D_0 + D_1) + D_2 in every lane.
+//  * K = 2: lanes 0, 1 take N0, N1 and subgroups 0, 1; both lanes then form
+//    D_2 and draw subgroup 2.  xor 1 gives D_0 + D_1; + D_2.
+// Lane 0 stores the link and counts; the values are those of the one-lane
+// pass, bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int kDppXor1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+constexpr int dpp_bcast(int k) { return k * 0x55; }  // quad_perm [k, k, k, k]
+
+template <int CTRL> __device__ __forceinline__ float dpp(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// M += (M of the partner lane)
+template <int CTRL, typename R> __device__ __forceinline__ void add_partner(M3<R> &m)
+{
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            m.e[r][c].re = m.e[r][c].re + dpp<CTRL>(m.e[r][c].re);
+            m.e[r][c].im = m.e[r][c].im + dpp<CTRL>(m.e[r][c].im);
+        }
+}
+template <int CTRL, typename R> __device__ __forceinline__ KPDraw<R> dpp_draw(const KPDraw<R> &d)
+{
+    return KPDraw<R>{dpp<CTRL>(d.q), dpp<CTRL>(d.u4sq), dpp<CTRL>(d.cth), dpp<CTRL>(d.sc), dpp<CTRL>(d.ss)};
+}
+template <typename R> __device__ __forceinline__ KPDraw<R> select_draw(bool p, const KPDraw<R> &a, const KPDraw<R> &b)
+{
+    return p ? a : b;
+}
+
+// Plane elements of x + nu, x - nu and x + MU - nu for a direction nu != MU
+// held at run time (one per lane), and whether x - nu lies in the other layer.
+template <int MU, bool DLT> struct NuElems {
+    int xp, xm, xmu_m;
+    bool cross;
+};
+template <int MU, bool DLT>
+__device__ __forceinline__ NuElems<MU, DLT> nu_elems(const Geom &g, const int x[4], int layer, int nu)
+{
+    const int L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], L3 = g.L[3];
+    const int xs = nu == 0 ? x[0] : nu == 1 ? x[1] : nu == 2 ? x[2] : x[3];
+    const int Ln = nu == 0 ? L0 : nu == 1 ? L1 : nu == 2 ? L2 : L3;
+    const int sn = nu == 0 ? 1 : nu == 1 ? L0 : nu == 2 ? L0 * L1 : L0 * L1 * L2;
+    const int fb = DLT ? (int)((g.flip >> nu) & 1u) : 0;
+    const bool top = xs == Ln - 1, bot = xs == 0;
+    const int wrap = (Ln - 1) * sn;
+    const int lex = lex_of(g, x);
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    int lmu = layer;
+    step<MU, +1, DLT>(g, y, lmu);  // x + MU; its nu coordinate is x's
+    const int lex_mu = lex_of(g, y);
+    const int lp = top ? lex - wrap : lex + sn, lyp = layer ^ (top ? fb : 0);
+    const int lm = bot ? lex + wrap : lex - sn, lym = layer ^ (bot ? fb : 0);
+    const int lmm = bot ? lex_mu + wrap : lex_mu - sn, lymm = lmu ^ (bot ? fb : 0);
+    NuElems<MU, DLT> r;
+    r.xp = DLT ? lyp * g.Vh + (lp >> 1) : lp >> 1;
+    r.xm = DLT ? lym * g.Vh + (lm >> 1) : lm >> 1;
+    r.xmu_m = DLT ? lymm * g.Vh + (lmm >> 1) : lmm >> 1;
+    r.cross = DLT && bot && fb;
+    return r;
+}
+
+// D_nu for a direction held at run time (the loads of staple_dir, addresses per lane).
+template <int MU, typename R, bool DLT, bool CROSS>
+__device__ __forceinline__ void staple_dir_rt(M3<R> &D, const store_t<R> *__restrict__ links, const Geom &g,
+                                              const int x[4], int layer, int par, int n, int nu, M3<R> &cross)
+{
+    const int opp = par ^ 1;
+    const NuElems<MU, DLT> ne = nu_elems<MU, DLT>(g, x, layer, nu);
+    const store_t<R> *umu = planes<R>(links, g, MU, opp);
+    const store_t<R> *unu_par = links + (size_t)(nu * 2 + par) * (size_t)g.stride * kEntries;
+    const store_t<R> *unu_opp = links + (size_t)(nu * 2 + opp) * (size_t)g.stride * kEntries;
+    M3<R> b, e, c, d, a, f;
+    load_link12_pair<R>(b, umu, ne.xp, e, umu, ne.xm);
+    load_link12_pair<R>(c, unu_par, n, d, unu_par, ne.xmu_m);
+    const M3<R> cb = mul_nn_su3(c, b);
+    const M3<R> ed = mul_nn_su3(e, d);
+    load_link12_pair<R>(a, unu_opp, nbr_elem<MU, +1, MU, 0, DLT>(g, x, layer), f, unu_opp, ne.xm);
+    staple_term<R, CROSS>(D, a, cb, ed, f, cross, CROSS && ne.cross);
+}
+
+// M *= s (s = 1 or 1/2: exact)
+template <typename R> __device__ __forceinline__ void scale_by(M3<R> &m, R s)
+{
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            m.e[r][c].re *= s;
+            m.e[r][c].im *= s;
+        }
+}
+
+// Lane q of the K-lane group of the link U_MU at pass-order position v.
+// MEAS: tr, trx as update_link, split over the lanes (each lane's share of S
+// and S_cross; the workgroup sum adds them up).
+template <int MU, typename R, bool DLT, bool MEAS, int K>
+__device__ __forceinline__ void update_link_lanes(store_t<R> *__restrict__ links, const Geom &g, int par, int v,
+                                                  int q, double beta, uint64_t sweep, uint64_t seed, bool active,
+                                                  int &att, int &acc, double &tr, double &trx)
+{
+    static_assert(K == 2 || K == 4, "2 or 4 lanes per link");
+    static_assert(!MEAS || MU > 0, "measured passes: MU = 1, 2, 3");
+    constexpr bool CROSS = MEAS && DLT;
+    constexpr int N0 = MU == 0 ? 1 : 0;
+    constexpr int N1 = MU <= 1 ? 2 : 1;
+    constexpr int N2 = MU <= 2 ? 3 : 2;
+    const int layer = DLT && v >= g.Vh ? 1 : 0;
+    int x[4];
+    const int i = order_site(g, par, v - layer * g.Vh, x);
+    const int n = layer * g.Vh + i;
+    const uint64_t site = (uint64_t)layer * (uint64_t)(2 * g.Vh) + (uint64_t)lex_of(g, x);
+    const uint64_t lid = 4 * site + MU;
+    const int sub = q < 2 ? q : 2;  // K = 4: lane 3 repeats lane 2
+    const int nu = sub == 0 ? N0 : (sub == 1 ? N1 : N2);
+    M3<R> A, S, Sx;
+    if constexpr (CROSS) set_zero(Sx);
+    __builtin_amdgcn_s_setprio(1);
+    staple_dir_rt<MU, R, DLT, CROSS>(A, links, g, x, layer, par, n, nu, Sx);
+    const KPDraw<R> mine = kp_draw<R>(seed, lid, sweep, sub, 0);
+    KPDraw<R> pre[3];
+    if constexpr (K == 4) {
+        if (q >= 2) {
+            scale_by(A, R(0.5));
+            if constexpr (CROSS) scale_by(Sx, R(0.5));
+        }
+        if constexpr (MEAS) {
+            S = A;
+            if (nu > MU) set_zero(S);
+            if constexpr (CROSS)
+                if (nu > MU) set_zero(Sx);
+        }
+        add_partner<kDppXor1>(A);
+        add_partner<kDppXor2>(A);
+        pre[0] = dpp_draw<dpp_bcast(0)>(mine);
+        pre[1] = dpp_draw<dpp_bcast(1)>(mine);
+        pre[2] = dpp_draw<dpp_bcast(2)>(mine);
+    } else {
+        if constexpr (MEAS) {
+            S = A;
+            if (nu > MU) set_zero(S);
+            if constexpr (CROSS)
+                if (nu > MU) set_zero(Sx);
+        }
+        add_partner<kDppXor1>(A);
+        M3<R> T;
+        // D_2 in both lanes; its measured share (MU = 3) and cross share in lane 0
+        {
+            const store_t<R> *umu = planes<R>(links, g, MU, par ^ 1);
+            M3<R> b, e;
+            load_link12_pair<R>(b, umu, nbr_elem<N2, +1, MU, 0, DLT>(g, x, layer), e, umu,
+                                nbr_elem<N2, -1, MU, 0, DLT>(g, x, layer));
+            staple_dir<MU, N2, R, DLT, CROSS && (N2 < MU)>(T, b, e, links, g, x, layer, par, n, Sx, q == 0);
+        }
+        add_to(A, T);
+        if constexpr (MEAS && N2 < MU)
+            if (q == 0) add_to(S, T);
+        const KPDraw<R> other = dpp_draw<kDppXor1>(mine);
+        pre[0] = select_draw(q == 0, mine, other);
+        pre[1] = select_draw(q == 0, other, mine);
+        pre[2] = kp_draw<R>(seed, lid, sweep, 2, 0);
+    }
+    store_t<R> *own = planes<R>(links, g, MU, par);
+    M3<R> U = load_link12_nt<R>(own, n);
+    __builtin_amdgcn_s_setprio(0);
+    int a_ = 0, c_ = 0;
+    heatbath<R, true, true>(U, A, beta, seed, lid, sweep, 1, a_, c_, pre);
+    if (active && q == 0) {
+        att += a_;
+        acc += c_;
+        if constexpr (sizeof(R) == 8)
+            store_link_nt<R>(own, n, U);
+        else
+            store_link<R>(own, n, U);
+    }
+    if constexpr (MEAS) {
+        tr = active ? retr_mul(U, S) : 0.0;
+        if constexpr (CROSS) trx = active ? retr_mul(U, Sx) : 0.0;
+    }
+}
+
+// One pass with K lanes per link in workgroups of kBlock threads (kBlock / K links).
+template <int MU, typename R, bool DLT, bool MEAS, int K>
+__global__ __launch_bounds__(kBlock, 2) void k_update_lanes(store_t<R> *__restrict__ links, const Geom g, const int par,
+                                                         const double beta, const uint64_t sweep, const uint64_t seed,
+                                                         unsigned long long *__restrict__ counters,
+                                                         double *__restrict__ meas)
+{
+    constexpr int kLinks = kBlock / K;
+    const int q = threadIdx.x & (K - 1);
+    const int nlinks = g.nlat * g.Vh;
+    int v = pass_tile(par) * kLinks + threadIdx.x / K;
+    const bool active = v < nlinks;
+    if (!active) v = nlinks - 1;  // every lane takes part in the exchanges; nothing is stored
+    int att = 0, acc = 0;
+    double tr = 0.0, trx = 0.0;
+    update_link_lanes<MU, R, DLT, MEAS, K>(links, g, par, v, q, beta, sweep, seed, active, att, acc, tr, trx);
+    count_block<kBlock>(att, acc, counters, blockIdx.x % kCounterSlots);
+    if constexpr (MEAS) {
+        const bool l1 = DLT && v >= g.Vh;
+        store_meas<kBlock>(meas, DLT, l1 ? trx : tr - trx, l1 ? tr - trx : trx);
+    }
 }
 
 // Polyakov loops along direction 3: thread (layer, x0, x1, x2) walks the
@@ -508,9 +898,10 @@ __global__ __launch_bounds__(kPassBlock, kPassWaves<R>) void k_update_batch(cons
     const int v = local * kPassBlock + threadIdx.x;
     const uint64_t sweep = J.sweep0 + (uint64_t)(step - J.admit_step);
     int att = 0, acc = 0;
+    double tr, trx;
     if (v < J.g.nlat * J.g.Vh)
         update_link<MU, R, HIT1, DLT, false, false, kStash, kPassBlock>((store_t<R> *)J.links, J.g, par, v, J.beta,
-                                                                        sweep, J.seed, J.nhit, att, acc, st);
+                                                                        sweep, J.seed, J.nhit, att, acc, st, tr, trx);
     count_block<kPassBlock>(att, acc, J.counters, local % kCounterSlots);
 }
 
@@ -750,97 +1141,24 @@ __global__ __launch_bounds__(kBlock) void k_plaq_partial(const store_t<R> *__res
     }
 }
 
-// Double-layered torus, fused measurement: the measured odd pass of MU files
-// the plaquette of the lower staple term of site x (based at y = x - nu) under
-// the layer of x.  y lies in the other layer exactly when the step crosses a
-// flipped boundary of direction nu, i.e. y_nu = L_nu - 1, y even.  This kernel
-// sums those plaquettes, planes (nu, mu) with mu > nu, per layer of y, so that
-// the per-layer sums can be moved to the right layer.  Grid (nblk,
-// kFaceGroups): blockIdx.y is one plane (nu, mu), so that each thread forms
-// one plaquette; thread q enumerates the face y_nu = L_nu - 1 (both parities;
-// odd sites contribute nothing: a grid of half the size over the even sites
-// alone took 13 instead of 9 us at 2 x 16^4); partials[2 (c nblk + b) + layer].
-template <int NU, int MU, typename R>
-__device__ __forceinline__ void face_plane(const store_t<R> *__restrict__ links, const Geom &g, long long q, double &s0,
-                                           double &s1)
-{
-    int y[4];
-    long long r = q;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        if (d == NU) continue;
-        y[d] = (int)(r % g.L[d]);
-        r /= g.L[d];
-    }
-    const int layer = (int)r;
-    y[NU] = g.L[NU] - 1;
-    if ((y[0] + y[1] + y[2] + y[3]) & 1) return;
-    const int n = layer * g.Vh + (lex_of(g, y) >> 1);
-    const double t = plaq_plane<NU, MU, R, true>(links, g, y, layer, 0, n);
-    if (layer)
-        s1 += t;
-    else
-        s0 += t;
-}
-
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_plaq_faces(const store_t<R> *__restrict__ links, const Geom g,
-                                                       double *__restrict__ partials)
-{
-    // plane c = blockIdx.y: (0,1) (0,2) (0,3) (1,2) (1,3) (2,3)
-    const int c = blockIdx.y;
-    const int nu = c < 3 ? 0 : (c < 5 ? 1 : 2);
-    double s0 = 0.0, s1 = 0.0;
-    const long long nface = (long long)g.nlat * (2LL * g.Vh / g.L[nu]);
-    const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (((g.flip >> nu) & 1) && q < nface) {
-        switch (c) {
-        case 0: face_plane<0, 1, R>(links, g, q, s0, s1); break;
-        case 1: face_plane<0, 2, R>(links, g, q, s0, s1); break;
-        case 2: face_plane<0, 3, R>(links, g, q, s0, s1); break;
-        case 3: face_plane<1, 2, R>(links, g, q, s0, s1); break;
-        case 4: face_plane<1, 3, R>(links, g, q, s0, s1); break;
-        default: face_plane<2, 3, R>(links, g, q, s0, s1); break;
-        }
-    }
-    const double b0 = block_sum(s0);
-    __syncthreads();
-    const double b1 = block_sum(s1);
-    if (threadIdx.x == 0) {
-        const size_t k = (size_t)c * gridDim.x + blockIdx.x;
-        partials[2 * k] = b0;
-        partials[2 * k + 1] = b1;
-    }
-}
-
-// Double-layered torus: per-layer plaquette sums of a measured sweep.  meas:
-// nmeas pairs (T_0, T_1) of the three measured passes; faces: nfaces pairs
-// (C_0, C_1).  sums[1 + l] = T_l + C_l - C_{1-l}, sums[0] = sums[1] + sums[2].
+// Double-layered torus: per-layer plaquette sums of a measured sweep from the
+// nmeas pairs (layer 0, layer 1) of the three measured passes, fixed order:
+// sums[1 + l] = the sum of layer l, sums[0] = sums[1] + sums[2].
 __global__ __launch_bounds__(kBlock) void k_measure_final_dlt(const double *__restrict__ meas, int nmeas,
-                                                              const double *__restrict__ faces, int nfaces,
                                                               double *__restrict__ sums)
 {
-    double t0 = 0.0, t1 = 0.0, c0 = 0.0, c1 = 0.0;
+    double t0 = 0.0, t1 = 0.0;
     for (int k = threadIdx.x; k < nmeas; k += kBlock) {
         t0 += meas[2 * k];
         t1 += meas[2 * k + 1];
     }
-    for (int k = threadIdx.x; k < nfaces; k += kBlock) {
-        c0 += faces[2 * k];
-        c1 += faces[2 * k + 1];
-    }
     const double T0 = block_sum(t0);
     __syncthreads();
     const double T1 = block_sum(t1);
-    __syncthreads();
-    const double C0 = block_sum(c0);
-    __syncthreads();
-    const double C1 = block_sum(c1);
     if (threadIdx.x == 0) {
-        const double p0 = T0 + C0 - C1, p1 = T1 + C1 - C0;
-        sums[0] = p0 + p1;
-        sums[1] = p0;
-        sums[2] = p1;
+        sums[0] = T0 + T1;
+        sums[1] = T0;
+        sums[2] = T1;
     }
 }
 
@@ -931,48 +1249,73 @@ hipError_t launch_start(int precision, void *links, const Geom &g, int hot, uint
     return hipGetLastError();
 }
 
-template <int MU, typename R>
+template <int MU, typename R, bool MEAS>
 static void update_launch(store_t<R> *links, const Geom &g, int par, double beta, uint64_t sweep, uint64_t seed,
-                          int nhit, unsigned long long *counters, hipStream_t s)
+                          int nhit, int lanes, unsigned long long *counters, double *meas, hipStream_t s)
 {
     const bool dlt = g.nlat == 2;
-    // one-wave workgroups on a single torus: a workgroup's LDS stash and slot
-    // are released as soon as its one wave ends (32^4: +1.4 %, 64^4: +2 %,
-    // 16^4: +7 % over four-wave workgroups); the double-layered torus keeps
-    // four-wave workgroups (-1 % with one wave)
+    const unsigned grid = (unsigned)pass_blocks(g, pass_links_per_block(g, lanes));
+    // several lanes per link for small passes (1-hit only; the host decides)
+    if (lanes == 4) {
+        if (dlt)
+            k_update_lanes<MU, R, true, MEAS, 4><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, counters, meas);
+        else
+            k_update_lanes<MU, R, false, MEAS, 4><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, counters, meas);
+        return;
+    }
+    if (lanes == 2) {
+        if (dlt)
+            k_update_lanes<MU, R, true, MEAS, 2><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, counters, meas);
+        else
+            k_update_lanes<MU, R, false, MEAS, 2><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, counters, meas);
+        return;
+    }
+    // one lane per link: one-wave workgroups on a single torus (a workgroup's
+    // LDS stash and slot are released as soon as its one wave ends: 32^4
+    // +1.4 %, 64^4 +2 %, 16^4 +7 % over four-wave workgroups); the
+    // double-layered torus keeps four-wave workgroups (-1 % with one wave)
     if (nhit == 1 && !dlt)
-        k_update<MU, R, true, false, false, kPassBlock>
-            <<<pass_blocks(g, kPassBlock), kPassBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters);
+        k_update<MU, R, true, false, MEAS, kPassBlock>
+            <<<grid, kPassBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters, meas);
     else if (nhit == 1)
-        k_update<MU, R, true, true><<<pass_blocks(g, kBlock), kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit,
-                                                                              counters);
+        k_update<MU, R, true, true, MEAS><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters, meas);
     else if (!dlt)
-        k_update<MU, R, false, false, false, kPassBlock>
-            <<<pass_blocks(g, kPassBlock), kPassBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters);
+        k_update<MU, R, false, false, MEAS, kPassBlock>
+            <<<grid, kPassBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters, meas);
     else
-        k_update<MU, R, false, true><<<pass_blocks(g, kBlock), kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit,
-                                                                               counters);
+        k_update<MU, R, false, true, MEAS><<<grid, kBlock, 0, s>>>(links, g, par, beta, sweep, seed, nhit, counters,
+                                                                    meas);
 }
 
 template <typename R>
 static void update_dispatch(store_t<R> *links, const Geom &g, int mu, int par, double beta, uint64_t sweep,
-                            uint64_t seed, int nhit, unsigned long long *counters, hipStream_t s)
+                            uint64_t seed, int nhit, int lanes, unsigned long long *counters, double *meas,
+                            hipStream_t s)
 {
+    if (meas) {  // measured: odd passes of mu = 1, 2, 3
+        switch (mu) {
+        case 1: update_launch<1, R, true>(links, g, 1, beta, sweep, seed, nhit, lanes, counters, meas, s); break;
+        case 2: update_launch<2, R, true>(links, g, 1, beta, sweep, seed, nhit, lanes, counters, meas, s); break;
+        default: update_launch<3, R, true>(links, g, 1, beta, sweep, seed, nhit, lanes, counters, meas, s); break;
+        }
+        return;
+    }
     switch (mu) {
-    case 0: update_launch<0, R>(links, g, par, beta, sweep, seed, nhit, counters, s); break;
-    case 1: update_launch<1, R>(links, g, par, beta, sweep, seed, nhit, counters, s); break;
-    case 2: update_launch<2, R>(links, g, par, beta, sweep, seed, nhit, counters, s); break;
-    default: update_launch<3, R>(links, g, par, beta, sweep, seed, nhit, counters, s); break;
+    case 0: update_launch<0, R, false>(links, g, par, beta, sweep, seed, nhit, lanes, counters, nullptr, s); break;
+    case 1: update_launch<1, R, false>(links, g, par, beta, sweep, seed, nhit, lanes, counters, nullptr, s); break;
+    case 2: update_launch<2, R, false>(links, g, par, beta, sweep, seed, nhit, lanes, counters, nullptr, s); break;
+    default: update_launch<3, R, false>(links, g, par, beta, sweep, seed, nhit, lanes, counters, nullptr, s); break;
     }
 }
 
 hipError_t launch_update(int precision, void *links, const Geom &g, int mu, int par, double beta, uint64_t sweep,
-                         uint64_t seed, int nhit, unsigned long long *counters, hipStream_t s)
+                         uint64_t seed, int nhit, int lanes, unsigned long long *counters, hipStream_t s)
 {
+    if (lanes != 1 && (nhit != 1 || (lanes != 2 && lanes != 4))) return hipErrorInvalidValue;
     if (precision == 64)
-        update_dispatch<double>((double2 *)links, g, mu, par, beta, sweep, seed, nhit, counters, s);
+        update_dispatch<double>((double2 *)links, g, mu, par, beta, sweep, seed, nhit, lanes, counters, nullptr, s);
     else
-        update_dispatch<float>((float2 *)links, g, mu, par, beta, sweep, seed, nhit, counters, s);
+        update_dispatch<float>((float2 *)links, g, mu, par, beta, sweep, seed, nhit, lanes, counters, nullptr, s);
     return hipGetLastError();
 }
 
@@ -1012,66 +1355,26 @@ hipError_t launch_update_batch(int precision, bool hit1, bool dlt, const BatchJo
     return hipGetLastError();
 }
 
-template <int MU, typename R>
-static void update_meas_launch(store_t<R> *links, const Geom &g, double beta, uint64_t sweep, uint64_t seed, int nhit,
-                               unsigned long long *counters, double *meas, hipStream_t s)
-{
-    // workgroups of meas_block_size(g) threads, as the unmeasured passes
-    const dim3 grid(meas_blocks(g));
-    const bool dlt = g.nlat == 2;
-    if (nhit == 1 && !dlt)
-        k_update<MU, R, true, false, true, kPassBlock><<<grid, kPassBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit,
-                                                                                  counters, meas);
-    else if (nhit == 1)
-        k_update<MU, R, true, true, true><<<grid, kBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit, counters,
-                                                                   meas);
-    else if (!dlt)
-        k_update<MU, R, false, false, true, kPassBlock><<<grid, kPassBlock, 0, s>>>(links, g, 1, beta, sweep, seed,
-                                                                                   nhit, counters, meas);
-    else
-        k_update<MU, R, false, true, true><<<grid, kBlock, 0, s>>>(links, g, 1, beta, sweep, seed, nhit, counters,
-                                                                    meas);
-}
-
-template <typename R>
-static void update_meas_dispatch(store_t<R> *links, const Geom &g, int mu, double beta, uint64_t sweep,
-                                 uint64_t seed, int nhit, unsigned long long *counters, double *meas, hipStream_t s)
-{
-    switch (mu) {
-    case 1: update_meas_launch<1, R>(links, g, beta, sweep, seed, nhit, counters, meas, s); break;
-    case 2: update_meas_launch<2, R>(links, g, beta, sweep, seed, nhit, counters, meas, s); break;
-    default: update_meas_launch<3, R>(links, g, beta, sweep, seed, nhit, counters, meas, s); break;
-    }
-}
-
-hipError_t launch_plaq_faces(int precision, const void *links, const Geom &g, double *partials, hipStream_t s)
-{
-    const dim3 grid(face_blocks(g), kFaceGroups);
-    if (precision == 64)
-        k_plaq_faces<double><<<grid, kBlock, 0, s>>>((const double2 *)links, g, partials);
-    else
-        k_plaq_faces<float><<<grid, kBlock, 0, s>>>((const float2 *)links, g, partials);
-    return hipGetLastError();
-}
-
 hipError_t launch_update_measured(int precision, void *links, const Geom &g, int mu, double beta, uint64_t sweep,
-                                  uint64_t seed, int nhit, unsigned long long *counters, double *meas, hipStream_t s)
+                                  uint64_t seed, int nhit, int lanes, unsigned long long *counters, double *meas,
+                                  hipStream_t s)
 {
-    if (mu < 1 || mu > 3) return hipErrorInvalidValue;
+    if (mu < 1 || mu > 3 || !meas) return hipErrorInvalidValue;
+    if (lanes != 1 && (nhit != 1 || (lanes != 2 && lanes != 4))) return hipErrorInvalidValue;
     if (precision == 64)
-        update_meas_dispatch<double>((double2 *)links, g, mu, beta, sweep, seed, nhit, counters, meas, s);
+        update_dispatch<double>((double2 *)links, g, mu, 1, beta, sweep, seed, nhit, lanes, counters, meas, s);
     else
-        update_meas_dispatch<float>((float2 *)links, g, mu, beta, sweep, seed, nhit, counters, meas, s);
+        update_dispatch<float>((float2 *)links, g, mu, 1, beta, sweep, seed, nhit, lanes, counters, meas, s);
     return hipGetLastError();
 }
 
-hipError_t launch_measure_final(const double *meas, const double *faces, const Geom &g, double *sums, hipStream_t s)
+hipError_t launch_measure_final(const double *meas, const Geom &g, int lanes, double *sums, hipStream_t s)
 {
+    const int nmeas = 3 * meas_blocks(g, lanes);
     if (g.nlat == 1)
-        k_sum_partials<<<1, kSumBlock, 0, s>>>(meas, 3 * meas_blocks(g), sums);
+        k_sum_partials<<<1, kSumBlock, 0, s>>>(meas, nmeas, sums);
     else
-        k_measure_final_dlt<<<1, kBlock, 0, s>>>(meas, 3 * meas_blocks(g), faces, kFaceGroups * face_blocks(g),
-                                                  sums);
+        k_measure_final_dlt<<<1, kBlock, 0, s>>>(meas, nmeas, sums);
     return hipGetLastError();
 }
 

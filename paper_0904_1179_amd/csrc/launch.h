@@ -23,8 +23,9 @@ struct BatchJob {
 };
 
 hipError_t launch_start(int precision, void *links, const Geom &g, int hot, uint64_t seed, hipStream_t s);
+// One checkerboard pass (mu, par) with `lanes` lanes per link (1; 2 or 4 with nhit = 1).
 hipError_t launch_update(int precision, void *links, const Geom &g, int mu, int par, double beta, uint64_t sweep,
-                         uint64_t seed, int nhit, unsigned long long *counters, hipStream_t s);
+                         uint64_t seed, int nhit, int lanes, unsigned long long *counters, hipStream_t s);
 // one pass (mu, par) of every job in d_jobs (device copy, sorted by tile_begin);
 // all jobs share `precision`; hit1: every job has nhit = 1; dlt: every job is
 // a double-layered torus (else every job is a single torus)
@@ -38,18 +39,14 @@ hipError_t launch_plaquette(int precision, const void *links, const Geom &g, dou
                             hipStream_t s, double *mean = nullptr);
 // The odd pass of mu (1, 2 or 3) that also stores, per workgroup, the sum of
 // its final plaquettes in the planes (nu, mu), nu < mu: meas[b] on a single
-// torus, meas[2 b + layer of the updated site] on a double-layered torus, b <
-// meas_blocks(g) (workgroups of meas_block_size(g) threads: one wave on a
-// single torus, four on a double-layered one).  The three passes write
-// consecutive slices of nlat * meas_blocks(g) doubles.  On a double-layered
-// torus launch_plaq_faces then sums the plaquettes those passes file under
-// the wrong layer (2 * kFaceGroups * face_blocks(g) doubles, one group per
-// plane (nu, mu)).  launch_measure_final adds everything up into sums[0]
-// (total) and sums[1 + l] (layer l).
+// torus, meas[2 b + l] for layer l on a double-layered torus (each plaquette
+// under its base site's layer), b < meas_blocks(g, lanes).  The three passes
+// write consecutive slices of nlat * meas_blocks(g, lanes) doubles, which
+// launch_measure_final adds up into sums[0] (total) and sums[1 + l] (layer l).
 hipError_t launch_update_measured(int precision, void *links, const Geom &g, int mu, double beta, uint64_t sweep,
-                                  uint64_t seed, int nhit, unsigned long long *counters, double *meas, hipStream_t s);
-hipError_t launch_plaq_faces(int precision, const void *links, const Geom &g, double *partials, hipStream_t s);
-hipError_t launch_measure_final(const double *meas, const double *faces, const Geom &g, double *sums, hipStream_t s);
+                                  uint64_t seed, int nhit, int lanes, unsigned long long *counters, double *meas,
+                                  hipStream_t s);
+hipError_t launch_measure_final(const double *meas, const Geom &g, int lanes, double *sums, hipStream_t s);
 // double-layered torus with per-layer couplings (a plaquette takes its base site's layer coupling)
 hipError_t launch_update_twob(int precision, void *links, const Geom &g, int mu, int par, double beta0,
                               double beta1, uint64_t sweep, uint64_t seed, int nhit, unsigned long long *counters,

@@ -113,6 +113,27 @@ size_t link_bytes_of(const su3_params *p, const Geom &g)
     return (size_t)8 * kEntries * (size_t)g.stride * (p->precision == 64 ? 16u : 8u);
 }
 
+// Passes of at most kLanes4Max links run with 4 lanes per link, of at most
+// kLanes2Max with 2, larger ones with 1.  Measured per pass (FP64): 2048 links
+// 11.3 us with 1 lane, 9.3 us with 4; 32768 links about even (FP32: 13.5 vs
+// 11 us with 2); 65536 links (2 x 16^4) 19 us with 1 lane, 21 us with 2, whose
+// two waves per SIMD then issue 1.6 times the instructions of one.
+constexpr long long kLanes4Max = 16384, kLanes2Max = 32768;
+
+int lanes_per_link(const Geom &g, int nhit, int requested)
+{
+    if (requested > 0) return requested;
+    if (nhit != 1) return 1;
+    const long long n = (long long)g.nlat * g.Vh;
+    return n <= kLanes4Max ? 4 : (n <= kLanes2Max ? 2 : 1);
+}
+
+int pass_links_per_block(const Geom &g, int lanes)
+{
+    if (lanes > 1) return kBlock / lanes;
+    return g.nlat == 1 ? kPassBlock : kBlock;
+}
+
 int pass_blocks(const Geom &g, int nb) { return (int)ceil_div((long long)g.nlat * g.Vh, nb); }
 
 int plaq_blocks(const Geom &g)
@@ -121,16 +142,11 @@ int plaq_blocks(const Geom &g)
     return (int)(need < kPlaqBlocksMax ? need : kPlaqBlocksMax);
 }
 
-int meas_block_size(const Geom &g) { return g.nlat == 1 ? kPassBlock : kBlock; }
-int meas_blocks(const Geom &g) { return pass_blocks(g, meas_block_size(g)); }
+int meas_blocks(const Geom &g, int lanes) { return pass_blocks(g, pass_links_per_block(g, lanes)); }
 
-int face_blocks(const Geom &g)
-{
-    int lmin = g.L[0];
-    if (g.L[1] < lmin) lmin = g.L[1];
-    if (g.L[2] < lmin) lmin = g.L[2];
-    return (int)ceil_div((long long)g.nlat * (2LL * g.Vh / lmin), kBlock);
-}
+// the most workgroups a measured pass can have: 64 links per workgroup
+// (one lane per link on a single torus, or 4 lanes per link)
+static int meas_blocks_max(const Geom &g) { return pass_blocks(g, 64); }
 
 int polyakov_blocks(const Geom &g) { return (int)ceil_div((long long)g.L[0] * g.L[1] * g.L[2], kBlock); }
 
@@ -138,15 +154,10 @@ int polyakov_blocks(const Geom &g) { return (int)ceil_div((long long)g.L[0] * g.
 // number of links that fail the unitarity check
 size_t meas_offset(const Geom &g) { return (size_t)round_up(kOffPartials + 2 * 8LL * g.nlat * plaq_blocks(g), 256); }
 
-size_t faces_offset(const Geom &g)
-{
-    return (size_t)round_up((long long)meas_offset(g) + 3 * 8LL * g.nlat * meas_blocks(g), 256);
-}
-
+// measured-pass partials: 3 passes x nlat doubles per workgroup
 size_t polyakov_offset(const Geom &g)
 {
-    const long long faces = g.nlat == 2 ? 2 * kFaceGroups * 8LL * face_blocks(g) : 0;
-    return (size_t)round_up((long long)faces_offset(g) + faces, 256);
+    return (size_t)round_up((long long)meas_offset(g) + 3 * 8LL * g.nlat * meas_blocks_max(g), 256);
 }
 
 size_t scratch_bytes_of(const Geom &g)

@@ -27,22 +27,23 @@ size_t link_bytes_of(const su3_params *p, const Geom &g);
 // ~1e-7 from the rounding of FP64-reunitarised rows.
 inline double unitarity_tol(int precision) { return precision == 64 ? 1e-10 : 1e-5; }
 
-// workgroups of nb threads covering the nlat * Vh links of one pass
+// Lanes per link of a pass: 1, or 2 or 4 for passes too small to fill the
+// GPU with one lane per link (1-hit only).  `requested` = 0 picks by the
+// number of links per pass; 1, 2, 4 force that count (2, 4 need nhit = 1).
+int lanes_per_link(const Geom &g, int nhit, int requested);
+// Links per workgroup of a pass with `lanes` lanes per link.
+int pass_links_per_block(const Geom &g, int lanes);
+// workgroups covering the nlat * Vh links of one pass, nb links each
 int pass_blocks(const Geom &g, int nb);
 // plaquette reduction: workgroups per layer
 int plaq_blocks(const Geom &g);
-// the measured passes of su3_sweep_measure: workgroup size and count
-int meas_block_size(const Geom &g);
-int meas_blocks(const Geom &g);
-// double-layered torus: workgroups per plane of the face-plaquette kernel
-constexpr int kFaceGroups = 6;
-int face_blocks(const Geom &g);
+// workgroups of a measured pass of su3_sweep_measure with `lanes` lanes per link
+int meas_blocks(const Geom &g, int lanes);
 // Polyakov loops: workgroups per layer
 int polyakov_blocks(const Geom &g);
 
 // scratch regions whose size depends on the lattice (bytes from the start)
 size_t meas_offset(const Geom &g);
-size_t faces_offset(const Geom &g);
 size_t polyakov_offset(const Geom &g);
 size_t scratch_bytes_of(const Geom &g);
 

@@ -56,6 +56,8 @@ def _load():
         "su3_set_sweep_index": (st, [vp, u64]),
         "su3_counters": (st, [vp, C.POINTER(u64), C.POINTER(u64), C.POINTER(u64)]),
         "su3_gauge_transform": (st, [vp, u64]),
+        "su3_set_lanes_per_link": (st, [vp, C.c_int32]),
+        "su3_get_lanes_per_link": (st, [vp, C.POINTER(C.c_int32)]),
         "su3_profile": (st, [vp, C.c_int32]),
         "su3_profile_read": (st, [vp, dp, C.POINTER(u64)]),
         "su3_destroy": (st, [vp]),
@@ -189,6 +191,16 @@ def su3_gauge_transform(ctx, gseed):
     _check(_lib.su3_gauge_transform(ctx, int(gseed)), "su3_gauge_transform")
 
 
+def su3_set_lanes_per_link(ctx, lanes):
+    _check(_lib.su3_set_lanes_per_link(ctx, int(lanes)), "su3_set_lanes_per_link")
+
+
+def su3_get_lanes_per_link(ctx):
+    v = C.c_int32(0)
+    _check(_lib.su3_get_lanes_per_link(ctx, C.byref(v)), "su3_get_lanes_per_link")
+    return v.value
+
+
 def su3_profile(ctx, enable):
     _check(_lib.su3_profile(ctx, int(bool(enable))), "su3_profile")
 
@@ -289,6 +301,14 @@ class Lattice:
 
     def gauge_transform(self, gseed):
         su3_gauge_transform(self.ctx, gseed)
+
+    @property
+    def lanes_per_link(self):
+        return su3_get_lanes_per_link(self.ctx)
+
+    @lanes_per_link.setter
+    def lanes_per_link(self, lanes):
+        su3_set_lanes_per_link(self.ctx, lanes)
 
     def profile(self, enable):
         su3_profile(self.ctx, enable)

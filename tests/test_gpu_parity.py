@@ -402,3 +402,58 @@ def test_non_finite_and_non_unitary_links_are_reported(hb, precision, scale):
     assert e.value.status == hb.su3hb.SU3_ENUMERIC and "2 links" in str(e.value)
     lat.set_links(good)
     lat.plaquette()
+
+
+# ------------------------------------------------------- lanes per link --
+
+@pytest.mark.parametrize("L,nlat,flip,precision,hot", [
+    ((8, 8, 8, 8), 1, None, 64, True),
+    ((6, 4, 10, 2), 1, None, 64, True),     # ragged: 240 links per pass, partial workgroups
+    ((2, 2, 2, 2), 1, None, 64, True),      # x + nu = x - nu
+    ((4, 4, 4, 6), 2, 0x7, 64, True),
+    ((4, 6, 4, 4), 2, 0xF, 64, False),
+    ((6, 4, 4, 4), 2, 0x5, 64, True),
+    ((8, 8, 8, 8), 1, None, 32, True),
+    ((4, 4, 6, 4), 2, 0x7, 32, True),
+])
+def test_lanes_per_link_give_identical_chains(hb, L, nlat, flip, precision, hot):
+    """The pass with 1, 2 and 4 lanes per link adds the staple in the same
+    order and uses the same draws: after plain and measured sweeps the links
+    are bit-identical and the counters equal; the fused plaquettes (summed
+    over lanes in another order) agree to 1e-13 and with su3_plaquette.  FP32
+    links: the fused plaquette takes its staple in FP32 (summed in FP32 with
+    one lane, per lane with several), so the bound is FP32 rounding, 1e-7."""
+    _say(f"lanes per link L={L} nlat={nlat} flip={flip} precision={precision}")
+    res = {}
+    for lanes in (1, 2, 4):
+        lat = hb.Lattice(L, nlat=nlat, flip_mask=flip, precision=precision, seed=7)
+        lat.lanes_per_link = lanes
+        assert lat.lanes_per_link == lanes
+        lat.start(hot)
+        lat.sweep(2, 5.7)
+        meas = lat.sweep_measure(2, 5.7)
+        res[lanes] = (lat.get_links(), lat.counters(), meas, lat.plaquette())
+    tol = 1e-13 if precision == 64 else 1e-7
+    for lanes in (2, 4):
+        d = np.abs(res[lanes][0] - res[1][0]).max()
+        assert np.array_equal(res[lanes][0], res[1][0]), f"{lanes} lanes: max |dU| = {d:.3e}"
+        assert res[lanes][1] == res[1][1]
+        assert np.abs(res[lanes][2] - res[1][2]).max() <= tol
+        assert np.abs(res[lanes][2][-1] - res[lanes][3]).max() <= tol
+    assert np.abs(res[1][2][-1] - res[1][3]).max() <= tol
+
+
+def test_lanes_per_link_choice_and_errors(hb):
+    assert hb.Lattice(8, seed=1).lanes_per_link == 4        # 2048 links per pass
+    assert hb.Lattice(16, seed=1).lanes_per_link == 2       # 32768
+    assert hb.Lattice(16, nlat=2, seed=1).lanes_per_link == 1  # 65536
+    assert hb.Lattice(32, seed=1).lanes_per_link == 1       # 524288
+    assert hb.Lattice(8, nhit=2, seed=1).lanes_per_link == 1
+    lat = hb.Lattice(8, nhit=2, seed=1)
+    for bad in (3, 8, -1):
+        with pytest.raises(hb.SU3Error):
+            lat.lanes_per_link = bad
+    with pytest.raises(hb.SU3Error) as e:
+        lat.lanes_per_link = 2  # several lanes need the 1-hit heat bath
+    assert e.value.status == -1
+    lat.lanes_per_link = 1
