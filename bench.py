@@ -139,11 +139,13 @@ def repeat_rates(lat, beta, repeats=10, sweeps=10):
 
 
 def device_warmup(ms, nbytes=256 << 20):
-    """Keep the GPU busy with the plain copy kernel for `ms` milliseconds.  A
-    GPU that was idle runs the first ~30 ms of sustained load up to 20 % slower
-    (power-management ramp; a second lattice allocated later runs at full speed
-    from its first sweep), so this runs before the timed steps.  It is not part
-    of the workload and not in the timed region."""
+    """Keep the GPU busy with the plain copy kernel for `ms` milliseconds.  On
+    a GPU that was idle, the passes of the first ~25 ms of sustained load run
+    up to 30 % slower (they start at full speed, slow down after ~2 ms and
+    recover over ~20 ms; a second lattice allocated later runs at full speed
+    from its first sweep, so the effect follows the device's load history, not
+    the allocation), so this runs before the timed steps.  It is not part of
+    the workload and not in the timed region."""
     import torch
 
     from paper_0904_1179_amd import su3_stream_copy
@@ -153,6 +155,8 @@ def device_warmup(ms, nbytes=256 << 20):
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     s = torch.cuda.current_stream()
+    su3_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream)
+    s.synchronize()  # start the clock after the first copy: lazy start-up costs are not GPU load
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < ms * 1e-3:
         for _ in range(4):

@@ -988,29 +988,6 @@ __global__ __launch_bounds__(kBlock) void k_gauge(store_t<R> *__restrict__ links
 // Grid (nblk, nlat); fixed per-thread order, wave shuffles and a fixed
 // per-block order, so the sum is bitwise reproducible.
 // ---------------------------------------------------------------------------
-// Re Tr U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+ = Re Tr P Q^+ with
-// P = U_mu(x) U_nu(x+mu), Q = U_nu(x) U_mu(x+nu), in FP64.
-template <int MU, int NU, typename R, bool DLT>
-__device__ __forceinline__ double plaq_plane(const store_t<R> *__restrict__ links, const Geom &g, const int x[4],
-                                             int layer, int par, int n)
-{
-    const int opp = par ^ 1;
-    const M3<double> umu = convert<double>(load_link12<R>(planes<R>(links, g, MU, par), n));
-    const M3<double> unu_xmu =
-        convert<double>(load_link12<R>(planes<R>(links, g, NU, opp), nbr_elem<MU, +1, NU, 0, DLT>(g, x, layer)));
-    const M3<double> unu = convert<double>(load_link12<R>(planes<R>(links, g, NU, par), n));
-    const M3<double> umu_xnu =
-        convert<double>(load_link12<R>(planes<R>(links, g, MU, opp), nbr_elem<NU, +1, MU, 0, DLT>(g, x, layer)));
-    const M3<double> P = mul_nn(umu, unu_xmu);
-    const M3<double> Q = mul_nn(unu, umu_xnu);
-    double s = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) s += P.e[a][b].re * Q.e[a][b].re + P.e[a][b].im * Q.e[a][b].im;
-    return s;
-}
-
 // Rows 0 and 1 of a link (row 2 never formed), in FP64.
 template <typename R> __device__ __forceinline__ M3<double> load_rows01(const store_t<R> *block, int n)
 {
@@ -1061,13 +1038,10 @@ __device__ __forceinline__ int link_bad(const M3<double> &u, double tol)
     return ok ? 0 : 1;
 }
 
-// The six planes of the site, and the check of its four own links.
-//  * FP64: every plane loads its four links; the compiler issues the loads of
-//    both sites of a thread at once (one wave per SIMD).
-//  * FP32: the four own links are loaded once and kept, and compiler-only
-//    fences between the planes hold the neighbour loads back (two waves per
-//    SIMD: 87 instead of 122 us at 32^4).  In FP64 the same scheme took the
-//    same time with 31 % more bytes fetched.
+// FP32 plaquette: the six planes of the site and the check of its four own
+// links.  The four own links are loaded once and kept, and compiler-only
+// fences between the planes hold the neighbour loads back (two waves per
+// SIMD: 87 instead of 122 us at 32^4).
 template <typename R, bool DLT>
 __device__ __forceinline__ double plaq_site(const store_t<R> *__restrict__ links, const Geom &g, int layer, int par,
                                            int i, double tol, int &bad)
@@ -1075,37 +1049,25 @@ __device__ __forceinline__ double plaq_site(const store_t<R> *__restrict__ links
     int x[4];
     site_coords(g, par, i, x);
     const int n = layer * g.Vh + i;
-    if constexpr (sizeof(R) == 8) {
-        double s = plaq_plane<0, 1, R, DLT>(links, g, x, layer, par, n);
-        s += plaq_plane<0, 2, R, DLT>(links, g, x, layer, par, n);
-        s += plaq_plane<1, 2, R, DLT>(links, g, x, layer, par, n);
-        s += plaq_plane<0, 3, R, DLT>(links, g, x, layer, par, n);
-        s += plaq_plane<1, 3, R, DLT>(links, g, x, layer, par, n);
-        s += plaq_plane<2, 3, R, DLT>(links, g, x, layer, par, n);
+    M3<double> U[4];
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu) bad += link_bad(load_rows01<R>(planes<R>(links, g, mu, par), n), tol);
-        return s;
-    } else {
-        M3<double> U[4];
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-            U[mu] = load_rows01<R>(planes<R>(links, g, mu, par), n);
-            bad += link_bad(U[mu], tol);
-        }
-        double s = plaq_plane_own<0, 1, R, DLT>(links, g, x, layer, par, U);
-        stash_fence();
-        s += plaq_plane_own<0, 2, R, DLT>(links, g, x, layer, par, U);
-        stash_fence();
-        s += plaq_plane_own<1, 2, R, DLT>(links, g, x, layer, par, U);
-        stash_fence();
-        s += plaq_plane_own<0, 3, R, DLT>(links, g, x, layer, par, U);
-        stash_fence();
-        s += plaq_plane_own<1, 3, R, DLT>(links, g, x, layer, par, U);
-        stash_fence();
-        s += plaq_plane_own<2, 3, R, DLT>(links, g, x, layer, par, U);
-        stash_fence();
-        return s;
+    for (int mu = 0; mu < 4; ++mu) {
+        U[mu] = load_rows01<R>(planes<R>(links, g, mu, par), n);
+        bad += link_bad(U[mu], tol);
     }
+    double s = plaq_plane_own<0, 1, R, DLT>(links, g, x, layer, par, U);
+    stash_fence();
+    s += plaq_plane_own<0, 2, R, DLT>(links, g, x, layer, par, U);
+    stash_fence();
+    s += plaq_plane_own<1, 2, R, DLT>(links, g, x, layer, par, U);
+    stash_fence();
+    s += plaq_plane_own<0, 3, R, DLT>(links, g, x, layer, par, U);
+    stash_fence();
+    s += plaq_plane_own<1, 3, R, DLT>(links, g, x, layer, par, U);
+    stash_fence();
+    s += plaq_plane_own<2, 3, R, DLT>(links, g, x, layer, par, U);
+    stash_fence();
+    return s;
 }
 
 // Grid (nblk, nlat).  Workgroup b (XCD-remapped) sums the contiguous run of
@@ -1131,6 +1093,74 @@ __global__ __launch_bounds__(kBlock) void k_plaq_partial(const store_t<R> *__res
             s += plaq_site<R, DLT>(links, g, layer, 0, i, tol, bad);
             s += plaq_site<R, DLT>(links, g, layer, 1, i, tol, bad);
         }
+    }
+    const double bs = block_sum(s);
+    __syncthreads();
+    const double bb = block_sum((double)bad);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.y * gridDim.x + blockIdx.x] = bs;
+        partials[(gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = bb;
+    }
+}
+
+// FP64 plaquette, one site per thread: thread w of a tile takes the site with
+// half-index i(w / 2) and parity w % 2, so the two threads of a half-index
+// read the two parity blocks at the same element.  The six planes (mu, nu)
+// each load their four links and form P and Q as SU(3) products (rows 0, 1,
+// row 2 rebuilt).  At 32^4: 168 us against 225 us for two sites per thread,
+// which needs 256 VGPRs plus 123 AGPRs (one wave per SIMD).  (Fencing the
+// planes to cut registers further pins every temporary and spills.)  FP32
+// keeps k_plaq_partial, whose fenced planes with held own links take 86 us
+// against 120 us.
+template <int MU, int NU, typename R, bool DLT>
+__device__ __forceinline__ double plaq_plane_su3(const store_t<R> *__restrict__ links, const Geom &g, const int x[4],
+                                                 int layer, int par, int n)
+{
+    const int opp = par ^ 1;
+    const M3<double> P = mul_nn_su3(
+        convert<double>(load_link12<R>(planes<R>(links, g, MU, par), n)),
+        convert<double>(load_link12<R>(planes<R>(links, g, NU, opp), nbr_elem<MU, +1, NU, 0, DLT>(g, x, layer))));
+    const M3<double> Q = mul_nn_su3(
+        convert<double>(load_link12<R>(planes<R>(links, g, NU, par), n)),
+        convert<double>(load_link12<R>(planes<R>(links, g, MU, opp), nbr_elem<NU, +1, MU, 0, DLT>(g, x, layer))));
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) s += P.e[a][b].re * Q.e[a][b].re + P.e[a][b].im * Q.e[a][b].im;
+    return s;
+}
+
+template <typename R, bool DLT>
+__device__ __forceinline__ double plaq_site1(const store_t<R> *__restrict__ links, const Geom &g, int layer,
+                                            int par, int i, double tol, int &bad)
+{
+    int x[4];
+    site_coords(g, par, i, x);
+    const int n = layer * g.Vh + i;
+    double s = plaq_plane_su3<0, 1, R, DLT>(links, g, x, layer, par, n);
+    s += plaq_plane_su3<0, 2, R, DLT>(links, g, x, layer, par, n);
+    s += plaq_plane_su3<1, 2, R, DLT>(links, g, x, layer, par, n);
+    s += plaq_plane_su3<0, 3, R, DLT>(links, g, x, layer, par, n);
+    s += plaq_plane_su3<1, 3, R, DLT>(links, g, x, layer, par, n);
+    s += plaq_plane_su3<2, 3, R, DLT>(links, g, x, layer, par, n);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) bad += link_bad(load_rows01<R>(planes<R>(links, g, mu, par), n), tol);
+    return s;
+}
+
+template <typename R, bool DLT>
+__global__ __launch_bounds__(kBlock, 2) void k_plaq_sites(const store_t<R> *__restrict__ links,
+                                                                       const Geom g, const int tiles_per_block,
+                                                                       const double tol, double *__restrict__ partials)
+{
+    const int layer = DLT ? (int)blockIdx.y : 0;
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    double s = 0.0;
+    int bad = 0;
+    for (int t = 0; t < tiles_per_block; ++t) {
+        const int w = (b * tiles_per_block + t) * kBlock + threadIdx.x;
+        if (w < 2 * g.Vh) s += plaq_site1<R, DLT>(links, g, layer, w & 1, order_index(g, w >> 1), tol, bad);
     }
     const double bs = block_sum(s);
     __syncthreads();
@@ -1382,17 +1412,21 @@ hipError_t launch_plaquette(int precision, const void *links, const Geom &g, dou
                             hipStream_t s, double *mean)
 {
     const int nblk = plaq_blocks(g);
-    const long long tiles = ((long long)g.Vh + kBlock - 1) / kBlock;
-    const int tpb = (int)((tiles + nblk - 1) / nblk);
     const dim3 grid(nblk, g.nlat);
     const bool dlt = g.nlat == 2;
     const double tol = unitarity_tol(precision);
     if (precision == 64) {
+        // one site per thread: tiles of kBlock sites
+        const long long tiles = (2LL * g.Vh + kBlock - 1) / kBlock;
+        const int tpb = (int)((tiles + nblk - 1) / nblk);
         if (dlt)
-            k_plaq_partial<double, true><<<grid, kBlock, 0, s>>>((const double2 *)links, g, tpb, tol, partials);
+            k_plaq_sites<double, true><<<grid, kBlock, 0, s>>>((const double2 *)links, g, tpb, tol, partials);
         else
-            k_plaq_partial<double, false><<<grid, kBlock, 0, s>>>((const double2 *)links, g, tpb, tol, partials);
+            k_plaq_sites<double, false><<<grid, kBlock, 0, s>>>((const double2 *)links, g, tpb, tol, partials);
     } else {
+        // two sites (one half-index) per thread
+        const long long tiles = ((long long)g.Vh + kBlock - 1) / kBlock;
+        const int tpb = (int)((tiles + nblk - 1) / nblk);
         if (dlt)
             k_plaq_partial<float, true><<<grid, kBlock, 0, s>>>((const float2 *)links, g, tpb, tol, partials);
         else
