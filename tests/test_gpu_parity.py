@@ -102,10 +102,16 @@ SWEEP_CASES = [
 ]
 
 
+@pytest.mark.parametrize("lanes", [0, 1])
 @pytest.mark.parametrize("L,nlat,flip,hot,beta,nhit,nsw", SWEEP_CASES)
-def test_sweeps_match_oracle(hb, L, nlat, flip, hot, beta, nhit, nsw):
-    _say(f"sweep parity L={L} nlat={nlat} flip={flip} hot={hot} beta={beta} nhit={nhit}")
+def test_sweeps_match_oracle(hb, L, nlat, flip, hot, beta, nhit, nsw, lanes):
+    """lanes 0: the lanes per link the library picks (4 or 2 on these small
+    lattices, 1 with nhit > 1); lanes 1: the one-lane pass kernel that large
+    lattices run, here on small and ragged ones."""
+    _say(f"sweep parity L={L} nlat={nlat} flip={flip} hot={hot} beta={beta} nhit={nhit} lanes={lanes}")
     lat = hb.Lattice(L, nlat=nlat, flip_mask=flip, nhit=nhit, seed=5)
+    if lanes:
+        lat.lanes_per_link = lanes
     ref = _oracle(L, nlat, flip, seed=5, nhit=nhit)
     lat.start(hot)
     ref.start(hot)
@@ -343,13 +349,13 @@ def test_dlt_sweep_measure_per_layer_against_oracle(hb, L, flip):
 
 # ------------------------------------------- full lattice, as the bench runs --
 
-@pytest.mark.parametrize("L,nlat", [(32, 1), (16, 2)])
+@pytest.mark.parametrize("L,nlat", [(32, 1), (16, 2), ((16, 16, 16, 18), 2)])
 def test_full_lattice_benched_call_against_oracle(hb, L, nlat):
     """The call the benchmark times (su3_sweep_measure) at the headline size
-    (32^4, FP64, hot start, seed 1, beta 5.7) and on the 2 x 16^4
-    double-layered torus: every link after sweeps 1 and 2 against the oracle
-    <= 1e-12, the counters exactly, each fused plaquette <= 1e-13; a single
-    two-sweep call ends bit-identical."""
+    (32^4, FP64, hot start, seed 1, beta 5.7) and on double-layered tori
+    (2 x 16^4; 2 x 16^3 x 18, whose domains differ): every link after sweeps 1
+    and 2 against the oracle <= 1e-12, the counters exactly, each fused
+    plaquette <= 1e-13; a single two-sweep call ends bit-identical."""
     _say(f"full-lattice benched call L={L} nlat={nlat}")
     lat = hb.Lattice(L, nlat=nlat, seed=1)
     ref = _oracle(L, nlat, seed=1)
@@ -415,6 +421,10 @@ def test_non_finite_and_non_unitary_links_are_reported(hb, precision, scale):
     ((6, 4, 4, 4), 2, 0x5, 64, True),
     ((8, 8, 8, 8), 1, None, 32, True),
     ((4, 4, 6, 4), 2, 0x7, 32, True),
+    # larger passes: 69632 and 73728 links
+    ((16, 16, 16, 34), 1, None, 64, True),
+    ((16, 16, 16, 18), 2, 0x7, 64, True),
+    ((16, 16, 16, 18), 2, 0x7, 32, True),
 ])
 def test_lanes_per_link_give_identical_chains(hb, L, nlat, flip, precision, hot):
     """The pass with 1, 2 and 4 lanes per link adds the staple in the same
