@@ -496,7 +496,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         if int(os.environ.get("RANK", "0")) == 0:
-            print("bench.py: this build runs one lattice on one GPU; --gpus above 1 is not supported "
+            print("bench.py: the benchmark runs one lattice on one GPU; --gpus above 1 is not supported "
                   "(independent chains or a halo-exchange decomposition would be needed)", file=sys.stderr)
         sys.exit(2)
 
