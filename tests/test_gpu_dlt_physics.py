@@ -1,5 +1,7 @@
 """GPU parity of the double-layered-torus extensions against the oracle:
-sweeps with per-layer couplings and Polyakov loops."""
+sweeps with per-layer couplings and Polyakov loops; and the GPU's gluing
+against its own periodic lattice (a one-flip double-layered torus is the
+periodic lattice of doubled extent)."""
 import numpy as np
 import pytest
 
@@ -56,3 +58,24 @@ def test_polyakov_matches_oracle(hb, L, nlat, mask, precision):
     ref.sweep(2, 5.7)
     tol = 1e-13 if precision == 64 else 1e-5
     assert np.abs(lat.polyakov() - ref.polyakov()).max() < tol
+
+
+@pytest.mark.parametrize("mu", [0, 1, 2, 3])
+def test_one_flip_dlt_is_the_doubled_torus_on_the_gpu(hb, mu):
+    """The GPU's double-layered torus with only the direction-mu boundary
+    flipped, after a sweep, and the GPU's periodic lattice of extent 2 L_mu
+    holding the same links: same plaquette and Polyakov loop to rounding.
+    Independent of the oracle: only the library's two geometries meet."""
+    from unfold import doubled_torus_map, unfold_links
+
+    L = (4, 2, 6, 4)
+    dlt = hb.Lattice(L, nlat=2, flip_mask=1 << mu, seed=17)
+    dlt.start(True)
+    dlt.sweep(1, 5.7)
+    L2, site = doubled_torus_map(L, mu)
+    pbc = hb.Lattice(L2, seed=17)
+    pbc.start(False)
+    pbc.set_links(unfold_links(dlt.get_links(), site))
+    p_dlt, p_pbc = dlt.plaquette(), pbc.plaquette()
+    assert abs(p_dlt[0] - p_pbc[0]) < 1e-14
+    assert abs(dlt.polyakov()[0] - pbc.polyakov()[0]) < 1e-14

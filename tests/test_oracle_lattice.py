@@ -1,5 +1,6 @@
 """Lattice-level pins of the oracle: geometry (PBC and the double-layered
-torus), cold/hot start, checkerboard independence, resume, strong coupling,
+torus, including the identity of a one-flip double-layered torus with the
+periodic lattice of doubled extent), cold/hot start, checkerboard independence, resume, strong coupling,
 the 1-hit acceptance the paper reports, and the stored per-sweep tables."""
 import json
 import os
@@ -9,6 +10,7 @@ import pytest
 
 from closed_forms import batch_mean_error, weyl_u
 from oracle import su3ref
+from unfold import doubled_torus_map, unfold_links
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
@@ -44,6 +46,35 @@ def test_dlt_layer_switches_only_across_flipped_boundaries(mask):
                 wraps = (coords[mu] == L[mu] - 1) if d > 0 else (coords[mu] == 0)
                 expect_layer = layer ^ (1 if (wraps and (mask >> mu) & 1) else 0)
                 assert y // V == expect_layer
+
+
+@pytest.mark.parametrize("mu", [0, 1, 2, 3])
+def test_dlt_with_one_flip_is_the_doubled_torus(mu):
+    """Crossing the direction-mu boundary switches the layer, so the two
+    layers form one periodic lattice of extent 2 L_mu in that direction (the
+    double-layered torus named in Sec. 1, glued as the oracle reads it, one
+    direction at a time).  With the same links in both
+    labellings the neighbours correspond, every staple is the same bits (same
+    links, same order of terms), and the plaquette and Polyakov loop agree to
+    rounding.  A wrong layer flip, a flip on the wrong boundary or a wrong
+    site in a staple term fails this."""
+    L = (4, 2, 6, 4)  # every extent distinct from its neighbour's
+    dlt = su3ref.Oracle(L, nlat=2, flip_mask=1 << mu, seed=13)
+    dlt.start(True)
+    dlt.sweep(1, 5.7)
+    L2, site = doubled_torus_map(L, mu)
+    pbc = su3ref.Oracle(L2, nlat=1, seed=13)
+    pbc.start(False)
+    pbc.set_links(unfold_links(dlt.links(), site))
+    for s in range(2 * dlt.V):
+        for nu in range(4):
+            for d in (+1, -1):
+                assert pbc.neighbor(site[s], nu, d) == site[dlt.neighbor(s, nu, d)]
+            assert np.array_equal(dlt.staple(s, nu), pbc.staple(site[s], nu)), (s, nu)
+    p_dlt, p_pbc = dlt.plaquette(), pbc.plaquette()
+    assert abs(p_dlt[0] - p_pbc[0]) < 1e-14
+    assert abs(p_dlt[0] - 0.5 * (p_dlt[1] + p_dlt[2])) < 1e-14
+    assert abs(dlt.polyakov()[0] - pbc.polyakov()[0]) < 1e-14
 
 
 def test_invalid_parameters_rejected():
