@@ -261,7 +261,9 @@ su3_status su3_stream_copy(void *dst, const void *src, size_t bytes, void *hip_s
  * checkerboard pass -- and retires
  * the jobs that reached their sweep count (final plaquette and heat-bath
  * counters kept, memory freed); su3_server_run does the same for several
- * sweeps per call.  A job's links get the same per-link
+ * sweeps per call.  A group of 1-hit jobs with at most 32768 links per pass
+ * in total runs two lanes per link (such a pass is bound by the latency of
+ * one update).  A job's links get the same per-link
  * arithmetic and the same keyed random numbers as a single lattice run with
  * su3_start/su3_sweep, so its result is the same alone and in the mix.
  * su3_server_step synchronises the server's stream.

@@ -866,7 +866,10 @@ __global__ __launch_bounds__(kBlock) void k_polyakov_final(const double *__restr
 // Batched pass: one launch updates the links U_MU of parity `par` of every
 // job in `jobs` (sorted by tile_begin).  The grid has one workgroup per tile
 // of the batch; logical tile t (pass_tile) belongs to the job whose tile range
-// holds t; job j is at sweep index sweep0 + (step - admit_step).
+// holds t; job j is at sweep index sweep0 + (step - admit_step).  A 1-hit job
+// with two lanes per link (the host's choice for a small batch, whose pass is
+// bound by the latency of one update) takes 32 links per workgroup and runs
+// update_link_lanes; its links are the same bits either way.
 template <int MU, typename R, bool HIT1, bool DLT>
 __global__ __launch_bounds__(kPassBlock, kPassWaves<R>) void k_update_batch(const BatchJob *__restrict__ jobs, const int njobs,
                                                              const long long step, const int par)
@@ -895,13 +898,23 @@ __global__ __launch_bounds__(kPassBlock, kPassWaves<R>) void k_update_batch(cons
     __syncthreads();
     const BatchJob &J = jobs[sj];
     const int local = t - J.tile_begin;
-    const int v = local * kPassBlock + threadIdx.x;
     const uint64_t sweep = J.sweep0 + (uint64_t)(step - J.admit_step);
+    const int nlinks = J.g.nlat * J.g.Vh;
     int att = 0, acc = 0;
     double tr, trx;
-    if (v < J.g.nlat * J.g.Vh)
-        update_link<MU, R, HIT1, DLT, false, false, kStash, kPassBlock>((store_t<R> *)J.links, J.g, par, v, J.beta,
-                                                                        sweep, J.seed, J.nhit, att, acc, st, tr, trx);
+    if (HIT1 && J.lanes == 2) {
+        int v = local * (kPassBlock / 2) + (int)(threadIdx.x >> 1);
+        const bool active = v < nlinks;
+        if (!active) v = nlinks - 1;  // both lanes take part in the exchanges; nothing is stored
+        update_link_lanes<MU, R, DLT, false, 2>((store_t<R> *)J.links, J.g, par, v, (int)(threadIdx.x & 1), J.beta,
+                                                sweep, J.seed, active, att, acc, tr, trx);
+    } else {
+        const int v = local * kPassBlock + threadIdx.x;
+        if (v < nlinks)
+            update_link<MU, R, HIT1, DLT, false, false, kStash, kPassBlock>((store_t<R> *)J.links, J.g, par, v,
+                                                                            J.beta, sweep, J.seed, J.nhit, att, acc,
+                                                                            st, tr, trx);
+    }
     count_block<kPassBlock>(att, acc, J.counters, local % kCounterSlots);
 }
 

@@ -19,6 +19,7 @@ struct BatchJob {
     uint64_t sweep0;               // sweep index at global step admit_step
     long long admit_step;
     int nhit;
+    int lanes;                     // lanes per link: 1, or 2 (nhit = 1 only)
     int tile_begin;                // first workgroup of this job in the launch
 };
 
@@ -28,7 +29,8 @@ hipError_t launch_update(int precision, void *links, const Geom &g, int mu, int 
                          uint64_t seed, int nhit, int lanes, unsigned long long *counters, hipStream_t s);
 // one pass (mu, par) of every job in d_jobs (device copy, sorted by tile_begin);
 // all jobs share `precision`; hit1: every job has nhit = 1; dlt: every job is
-// a double-layered torus (else every job is a single torus)
+// a double-layered torus (else every job is a single torus).  A job with
+// `lanes` lanes per link takes ceil(lanes * nlat * Vh / 64) workgroups.
 hipError_t launch_update_batch(int precision, bool hit1, bool dlt, const BatchJob *d_jobs, int njobs, int ntiles,
                                long long step, int mu, int par, hipStream_t s);
 // Plaquette sums of the whole lattice into sums[0..3] (total, per layer,

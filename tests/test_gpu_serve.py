@@ -73,6 +73,25 @@ def test_each_result_identical_alone_and_in_the_mix(hb, sweeps_per_call):
         assert r["sweeps_done"] == spec[4]
 
 
+def test_lanes_per_link_follow_the_batch_size(hb):
+    """A 1-hit batch of at most 32768 links per pass runs two lanes per link,
+    a larger one one lane.  The 16^4 jobs (32768 links) share their batch
+    with a smaller job first (one lane) and finish alone (two lanes): every
+    result is still bit-identical to the job run alone."""
+    from paper_0904_1179_amd import serve
+
+    mix = [(16, 1, 32, 5.7, 6, 41, 1, 1), (6, 1, 32, 5.9, 2, 42, 1, 1),
+           (16, 1, 64, 6.0, 4, 43, 1, 1), (8, 1, 64, 5.6, 2, 44, 0, 1)]
+    jobs = [{"id": k, "arrival": 0.0, "L": L, "nlat": nlat, "precision": prec, "beta": beta, "nsweeps": nsw,
+             "seed": seed, "hot": hot, "nhit": nhit} for k, (L, nlat, prec, beta, nsw, seed, hot, nhit) in
+            enumerate(mix)]
+    recs, _ = serve.run_stream(jobs, arena_bytes=256 << 20, max_active=8, realtime=False, sweeps_per_call=1)
+    for k, spec in enumerate(mix):
+        p_alone, cnt_alone = _alone(hb, *spec)
+        assert np.array_equal(np.array(recs[k]["plaquette"][:2]), p_alone), (spec, recs[k]["plaquette"], p_alone)
+        assert (recs[k]["kp_attempts"], recs[k]["kp_accepts"]) == cnt_alone
+
+
 def test_admission_limited_by_footprint_and_slots(hb):
     from paper_0904_1179_amd import serve
 
