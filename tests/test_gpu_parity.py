@@ -126,6 +126,46 @@ def test_sweeps_match_oracle(hb, L, nlat, flip, hot, beta, nhit, nsw, lanes):
         assert (att, acc) == ref.counters()
 
 
+@pytest.mark.parametrize("lanes", [0, 1])
+def test_zero_staple_skips_every_subgroup(hb, lanes):
+    """The degenerate case of the heat bath: a staple that is exactly zero
+    (k = 0 in every subgroup, nothing to sample) leaves the link as it is and
+    counts no attempt.  On a cold 4^4 lattice the six staple terms of U_0 at
+    the origin are set to diagonal SU(3) matrices with entries +-1, +-i that
+    sum to zero entry by entry (exact in floating point); U_0 at the origin is
+    updated in the first pass of the sweep, so it sees that staple.  The sweep
+    matches the oracle (links <= 1e-12, counters exactly) and that link stays
+    the identity, bit for bit."""
+    from oracle import su3ref
+
+    L = 4
+    # up_nu = U_nu(x + 0) and dn_nu = U_nu(x - nu) when every other link is 1
+    terms = {1: ((1, 1, 1), (1, -1, -1)), 2: ((-1, 1, -1), (-1, 1j, 1j)), 3: ((1j, -1j, 1), (-1j, -1, -1j))}
+    lat = hb.Lattice(L, seed=21)
+    ref = su3ref.Oracle(L, seed=21)
+    if lanes:
+        lat.lanes_per_link = lanes
+    lat.start(False)
+    ref.start(False)
+    links = ref.links().copy()
+    minus = {1: (L - 1) * L, 2: (L - 1) * L * L, 3: (L - 1) * L ** 3}  # lex of x - nu from the origin
+    for nu, (up, dn) in terms.items():
+        links[4 * 1 + nu] = su3ref._mat(np.diag(np.array(up, dtype=complex)))
+        links[4 * minus[nu] + nu] = su3ref._mat(np.diag(np.array(dn, dtype=complex)))
+    assert np.abs(sum(np.array(u, dtype=complex) + np.array(d, dtype=complex) for u, d in terms.values())).max() == 0
+    lat.set_links(links)
+    ref.set_links(links)
+    lat.sweep(1, 5.7)
+    ref.sweep(1, 5.7)
+    got = lat.get_links()
+    assert np.abs(got - ref.links()).max() < 1e-12
+    assert lat.counters()[1:] == ref.counters()
+    assert np.array_equal(got[0], su3ref._mat(np.eye(3, dtype=complex)))
+    assert np.array_equal(ref.links()[0], su3ref._mat(np.eye(3, dtype=complex)))
+    # every other link got its three attempts
+    assert ref.counters()[0] == 3 * (4 * L ** 4 - 1)
+
+
 def test_m1_plaquette_table(hb):
     """8^4, beta 5.7, cold, 32 sweeps, seed 1: per-sweep plaquette and counters
     against the stored oracle table.  Rounding differences grow along the
