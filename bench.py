@@ -90,13 +90,14 @@ def stored_traffic(name):
         return None
 
 
-def run_gpu(L, precision, steps, warmup, beta, seed=1):
+def run_gpu(L, precision, steps, warmup, beta, seed=1, device_warmup_ms=0.0):
     import torch
 
     from paper_0904_1179_amd import Lattice
 
     lat = Lattice(L, nlat=1, precision=precision, seed=seed)
     lat.start(hot=True)
+    warmed_ms = device_warmup(device_warmup_ms, L, precision, beta)
     if warmup > 0:
         lat.sweep_measure(warmup, beta)
     torch.cuda.synchronize()
@@ -113,7 +114,7 @@ def run_gpu(L, precision, steps, warmup, beta, seed=1):
     full = float(lat.plaquette()[0])
     V = L ** 4
     return {"seconds": t1 - t0, "updates": 4 * V * steps, "pass_ms": pass_ms / max(passes, 1), "passes": passes,
-            "plaquette": plaq, "plaquette_full_kernel": full, "lattice": lat}
+            "plaquette": plaq, "plaquette_full_kernel": full, "lattice": lat, "device_warmup_ms": warmed_ms}
 
 
 def repeat_rates(lat, beta, repeats=10, sweeps=10):
@@ -138,31 +139,32 @@ def repeat_rates(lat, beta, repeats=10, sweeps=10):
             "timing": "HIP events around su3_sweep on the lattice's stream, each from a fresh hot start"}
 
 
-def device_warmup(ms, nbytes=256 << 20):
-    """Keep the GPU busy with the plain copy kernel for `ms` milliseconds.  On
-    a GPU that was idle, the passes of the first ~25 ms of sustained load run
-    up to 30 % slower (they start at full speed, slow down after ~2 ms and
-    recover over ~20 ms; a second lattice allocated later runs at full speed
-    from its first sweep, so the effect follows the device's load history, not
-    the allocation), so this runs before the timed steps.  It is not part of
-    the workload and not in the timed region."""
+def device_warmup(ms, L, precision, beta):
+    """Keep the GPU busy for `ms` milliseconds with the workload's own pass
+    kernels, on a scratch lattice of the same size and precision (hot start,
+    discarded afterwards; the timed lattice's chain is not touched).  On a
+    GPU that was idle, or that ran other kernels, the passes of the first
+    ~25 ms of sustained load run up to 30 % slower (they start at full speed,
+    slow down after ~2 ms and recover over ~20 ms; a second lattice allocated
+    later runs at full speed from its first sweep, so the effect follows the
+    device's load history, not the allocation; a warm-up with the copy kernel
+    left the timed steps ~3 % slower than one with the pass kernels).  It is
+    not part of the workload and not in the timed region."""
     import torch
 
-    from paper_0904_1179_amd import su3_stream_copy
+    from paper_0904_1179_amd import Lattice
 
     if ms <= 0:
         return 0.0
-    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    dst = torch.empty_like(src)
-    s = torch.cuda.current_stream()
-    su3_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream)
-    s.synchronize()  # start the clock after the first copy: lazy start-up costs are not GPU load
+    lat = Lattice(L, nlat=1, precision=precision, seed=0x5eed)
+    lat.start(hot=True)
+    lat.sweep(1, beta)
+    torch.cuda.synchronize()  # start the clock after the first sweep: lazy start-up costs are not GPU load
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < ms * 1e-3:
-        for _ in range(4):
-            su3_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream)
-        s.synchronize()
-    del src, dst
+        lat.sweep(4, beta)
+        torch.cuda.synchronize()
+    del lat
     return (time.perf_counter() - t0) * 1e3
 
 
@@ -489,7 +491,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the mixed job stream")
     ap.add_argument("--no-configs", action="store_true", help="skip the other configurations (8^4, 16^4, 2x16^4 DLT, 64^4)")
     ap.add_argument("--device-warmup-ms", type=float, default=100.0,
-                    help="busy the GPU with the copy kernel this long before the first lattice (power ramp)")
+                    help="busy the GPU this long with the pass kernels on a scratch lattice before the timed "
+                         "lattice's warm-up steps (power ramp)")
     ap.add_argument("--startup-trace", action="store_true",
                     help="only trace the sweep time from the process's first sweep (two lattices, clocks sampled)")
     args = ap.parse_args()
@@ -507,8 +510,8 @@ def main():
     if args.startup_trace:
         print(json.dumps(startup_trace(L, beta)), flush=True)
         return
-    warmed_ms = device_warmup(args.device_warmup_ms)
-    main_run = run_gpu(L, prec, args.steps, args.warmup, beta)
+    main_run = run_gpu(L, prec, args.steps, args.warmup, beta, device_warmup_ms=args.device_warmup_ms)
+    warmed_ms = main_run["device_warmup_ms"]
     ups = main_run["updates"] / main_run["seconds"]
     pass_s = main_run["pass_ms"] * 1e-3
     links_per_pass = L ** 4 // 2
@@ -548,7 +551,7 @@ def main():
            "roofline": roofline}
 
     if not args.no_fp32 and prec == 64:
-        r32 = run_gpu(L, 32, args.steps, args.warmup, beta)
+        r32 = run_gpu(L, 32, args.steps, args.warmup, beta, device_warmup_ms=args.device_warmup_ms)
         del r32["lattice"]
         v32 = r32["updates"] / r32["seconds"]
         pass32 = r32["pass_ms"] * 1e-3
