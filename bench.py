@@ -41,6 +41,10 @@ REAL_BYTES = {64: 8, 32: 4}
 LINK_REALS, STORED_REALS, TRANSFERS_PER_UPDATE = 18, 12, 9
 
 
+# device warm-up before each of the other configurations' timed sweeps (milliseconds)
+CONFIG_WARMUP_MS = 50.0
+
+
 def bytes_per_update(precision):
     """Algorithmic bytes per link update: 9 transfers of an 18-real link."""
     return TRANSFERS_PER_UPDATE * LINK_REALS * REAL_BYTES[precision]
@@ -139,10 +143,11 @@ def repeat_rates(lat, beta, repeats=10, sweeps=10):
             "timing": "HIP events around su3_sweep on the lattice's stream, each from a fresh hot start"}
 
 
-def device_warmup(ms, L, precision, beta):
+def device_warmup(ms, L, precision, beta, nlat=1, flip_mask=None, measure=False, betas=None):
     """Keep the GPU busy for `ms` milliseconds with the workload's own pass
-    kernels, on a scratch lattice of the same size and precision (hot start,
-    discarded afterwards; the timed lattice's chain is not touched).  On a
+    kernels, on a scratch lattice of the same shape and precision (hot start,
+    discarded afterwards; the timed lattice's chain is not touched): sweeps,
+    sweeps with the plaquette (measure) or sweeps with two couplings (betas).  On a
     GPU that was idle, or that ran other kernels, the passes of the first
     ~25 ms of sustained load run up to 30 % slower (they start at full speed,
     slow down after ~2 ms and recover over ~20 ms; a second lattice allocated
@@ -156,13 +161,22 @@ def device_warmup(ms, L, precision, beta):
 
     if ms <= 0:
         return 0.0
-    lat = Lattice(L, nlat=1, precision=precision, seed=0x5eed)
+    lat = Lattice(L, nlat=nlat, precision=precision, seed=0x5eed, flip_mask=flip_mask)
     lat.start(hot=True)
-    lat.sweep(1, beta)
+
+    def run(n):
+        if betas is not None:
+            lat.sweep_betas(n, *betas)
+        elif measure:
+            lat.sweep_measure(n, beta)
+        else:
+            lat.sweep(n, beta)
+
+    run(1)
     torch.cuda.synchronize()  # start the clock after the first sweep: lazy start-up costs are not GPU load
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < ms * 1e-3:
-        lat.sweep(4, beta)
+        run(4)
         torch.cuda.synchronize()
     del lat
     return (time.perf_counter() - t0) * 1e3
@@ -220,18 +234,22 @@ def chain_deviation(p32, p64, bound=1e-5):
             "onset_sweep": None if onset is None else onset + 1, "bound": bound}
 
 
-def config_rate(L, nlat, precision, beta, sweeps, seed=1, flip_mask=None, hot=True, untimed=1, every=True):
+def config_rate(L, nlat, precision, beta, sweeps, seed=1, flip_mask=None, hot=True, untimed=1, every=True,
+                warmup_ms=CONFIG_WARMUP_MS):
     """Link updates/s of `sweeps` sweeps on one more workload configuration,
-    after the start and `untimed` untimed sweeps, with the plaquette after
-    every sweep (every=True) or once after the last (outside the timed
-    region); also the algorithmic bytes per second of the passes and the
-    plaquettes (all sweeps with every=True, kept for the FP32 comparison)."""
+    after the start, a device warm-up with the same kernels on a scratch
+    lattice (these timed regions last only milliseconds) and `untimed`
+    untimed sweeps, with the plaquette after every sweep (every=True) or once
+    after the last (outside the timed region); also the algorithmic bytes per
+    second of the passes and the plaquettes (all sweeps with every=True, kept
+    for the FP32 comparison)."""
     import torch
 
     from paper_0904_1179_amd import Lattice
 
     lat = Lattice(L, nlat=nlat, precision=precision, seed=seed, flip_mask=flip_mask)
     lat.start(hot=hot)
+    device_warmup(warmup_ms, L, precision, beta, nlat=nlat, flip_mask=flip_mask, measure=every)
     if untimed:
         lat.sweep(untimed, beta)
     torch.cuda.synchronize()
@@ -254,9 +272,10 @@ def config_rate(L, nlat, precision, beta, sweeps, seed=1, flip_mask=None, hot=Tr
             "_plaquette_series": [float(x[0]) for x in plaq]}
 
 
-def two_coupling_rate(L, beta0, beta1, sweeps, seed=1):
+def two_coupling_rate(L, beta0, beta1, sweeps, seed=1, warmup_ms=CONFIG_WARMUP_MS):
     """Double-layered torus (flip mask 0x7) with per-layer couplings: link
-    updates/s of `sweeps` sweeps (one untimed sweep first), then the per-layer
+    updates/s of `sweeps` sweeps (a device warm-up with the same kernels on a
+    scratch lattice and one untimed sweep first), then the per-layer
     plaquettes and Polyakov loops."""
     import torch
 
@@ -264,6 +283,7 @@ def two_coupling_rate(L, beta0, beta1, sweeps, seed=1):
 
     lat = Lattice(L, nlat=2, precision=64, seed=seed, flip_mask=0x7)
     lat.start(hot=True)
+    device_warmup(warmup_ms, L, 64, beta0, nlat=2, flip_mask=0x7, betas=(beta0, beta1))
     lat.sweep_betas(1, beta0, beta1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
