@@ -34,7 +34,7 @@
  *
  * Threading: one context per stream.  Distinct contexts are independent and
  * may be used from different threads; one context must not be used from two
- * threads at once.
+ * threads at once.  The same holds for a job server.
  */
 #ifndef SU3HB_H
 #define SU3HB_H
@@ -305,7 +305,14 @@ su3_status su3_server_step(su3_server *s, int32_t *n_active, int32_t *n_queued, 
  * SU3_EINVAL if max_sweeps < 1. */
 su3_status su3_server_run(su3_server *s, int32_t max_sweeps, int32_t *n_active, int32_t *n_queued,
                           int32_t *n_finished);
+/* State, sweeps done and, once done, the final plaquette and counters of a job.
+ * SU3_EINVAL for an unknown (or released) id. */
 su3_status su3_server_poll(su3_server *s, int64_t job_id, su3_job_result *out);
+/* Drop the record of a finished job (after its result was polled): the server
+ * keeps every job's record until then, so a long-running caller releases the
+ * jobs it has read.  SU3_ESTATE if the job is not done, SU3_EINVAL for an
+ * unknown id. */
+su3_status su3_server_release(su3_server *s, int64_t job_id);
 /* Copy an active job's links to host memory in the canonical FP64 layout of
  * su3_get_links (n_doubles = 72 V nlat of the job), between server calls:
  * the read-back for checking a served job link by link.  SU3_ESTATE if the

@@ -366,6 +366,16 @@ su3_status su3_server_poll(su3_server *s, int64_t job_id, su3_job_result *out)
     return SU3_OK;
 }
 
+su3_status su3_server_release(su3_server *s, int64_t job_id)
+{
+    if (!s) return fail(SU3_EINVAL, "server is NULL");
+    auto it = s->jobs.find(job_id);
+    if (it == s->jobs.end()) return fail(SU3_EINVAL, "unknown job id");
+    if (it->second.state != SU3_JOB_DONE) return fail(SU3_ESTATE, "only a finished job can be released");
+    s->jobs.erase(it);
+    return SU3_OK;
+}
+
 su3_status su3_server_get_links(su3_server *s, int64_t job_id, double *host, size_t n_doubles)
 {
     if (!s || !host) return fail(SU3_EINVAL, "server and host must not be NULL");

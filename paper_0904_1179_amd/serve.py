@@ -34,6 +34,7 @@ for _name, _res, _args in (
         ("su3_server_step", _st, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         ("su3_server_run", _st, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         ("su3_server_poll", _st, [_vp, C.c_int64, C.POINTER(su3_job_result)]),
+        ("su3_server_release", _st, [_vp, C.c_int64]),
         ("su3_server_get_links", _st, [_vp, C.c_int64, C.POINTER(C.c_double), C.c_size_t]),
         ("su3_server_stats", _st, [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(C.c_uint64)]),
         ("su3_server_destroy", _st, [_vp])):
@@ -92,6 +93,10 @@ class Server:
         return {"state": r.state, "sweeps_done": r.sweeps_done, "plaquette": list(r.plaquette),
                 "kp_attempts": r.kp_attempts, "kp_accepts": r.kp_accepts, "bad_links": r.bad_links}
 
+    def release(self, jid):
+        """su3_server_release: drop a finished job's record."""
+        _hb._check(_lib.su3_server_release(self.h, int(jid)), "su3_server_release")
+
     def get_links(self, jid, n_doubles):
         """su3_server_get_links: an active job's links, canonical FP64 layout, shape (n_doubles // 18, 18)."""
         out = np.empty(int(n_doubles), dtype=np.float64)
@@ -120,7 +125,7 @@ def run_stream(jobs, arena_bytes=4 << 30, max_active=256, realtime=True, sweeps_
     stream started) and final plaquette/counters."""
     srv = Server(arena_bytes, max_active)
     order = sorted(jobs, key=lambda j: j["arrival"])
-    ids, recs = {}, {}
+    ids, recs, pending = {}, {}, set()
     nxt, done = 0, 0
     t0 = time.perf_counter()
     while done < len(order):
@@ -130,20 +135,21 @@ def run_stream(jobs, arena_bytes=4 << 30, max_active=256, realtime=True, sweeps_
             jid = srv.submit(make_job(j["L"], j["beta"], j["nsweeps"], j["seed"], j["precision"], j.get("nlat", 1),
                                       j.get("flip_mask"), j.get("nhit", 1), j.get("hot", 1)))
             ids[jid] = j
+            pending.add(jid)
             recs[j["id"]] = {"arrival": j["arrival"] if realtime else 0.0, "submitted": now}
             nxt += 1
         active, queued, finished = srv.run(sweeps_per_call)
         if finished:
             t = time.perf_counter() - t0
-            for jid, j in ids.items():
-                r = recs[j["id"]]
-                if "done" in r:
-                    continue
+            for jid in sorted(pending):
                 res = srv.poll(jid)
                 if res["state"] == DONE:
+                    r = recs[ids[jid]["id"]]
                     r.update(res)
                     r["done"] = t
                     r["latency"] = t - r["arrival"]
+                    srv.release(jid)  # the server keeps no record of it from here on
+                    pending.discard(jid)
                     done += 1
         if active == 0 and queued == 0 and nxt < len(order):
             time.sleep(max(0.0, order[nxt]["arrival"] - (time.perf_counter() - t0)))

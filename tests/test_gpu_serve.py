@@ -123,6 +123,32 @@ def test_admission_limited_by_footprint_and_slots(hb):
     assert srv2.step()[:2] == (3, 2)
 
 
+def test_release_drops_only_finished_jobs(hb):
+    from paper_0904_1179_amd import serve
+
+    srv = serve.Server(arena_bytes=16 << 20, max_active=2)
+    a = srv.submit(serve.make_job(4, 5.7, 1, seed=1))
+    b = srv.submit(serve.make_job(4, 5.7, 3, seed=2))
+    with pytest.raises(hb.SU3Error) as e:
+        srv.release(a)  # queued
+    assert e.value.status == -4
+    srv.step()
+    assert srv.poll(a)["state"] == serve.DONE and srv.poll(b)["state"] == serve.ACTIVE
+    with pytest.raises(hb.SU3Error) as e:
+        srv.release(b)  # active
+    assert e.value.status == -4
+    srv.release(a)
+    with pytest.raises(hb.SU3Error) as e:
+        srv.poll(a)
+    assert e.value.status == -1
+    with pytest.raises(hb.SU3Error) as e:
+        srv.release(a)
+    assert e.value.status == -1
+    srv.step()
+    srv.step()
+    assert srv.poll(b)["state"] == serve.DONE
+
+
 def test_invalid_jobs_rejected(hb):
     from paper_0904_1179_amd import serve
 
