@@ -226,7 +226,9 @@ su3_status su3_gauge_transform(su3_ctx *c, uint64_t gseed);
  * sweep with index s when 2 mu + parity = s mod 8, so eight consecutive sweeps
  * time each of the eight passes once at two event records per sweep.
  * su3_profile_read synchronises and returns the summed time of the timed
- * passes in ms and their number since the last read (then resets both). */
+ * passes in ms and their number since the last read (then resets both).
+ * The context holds two HIP events per timed sweep until the next read and
+ * reuses them afterwards: read at least every few ten thousand sweeps. */
 su3_status su3_profile(su3_ctx *c, int32_t enable);
 su3_status su3_profile_read(su3_ctx *c, double *total_ms, uint64_t *passes);
 
