@@ -79,8 +79,8 @@ typedef struct {
  * Scratch: heat-bath counter slots (64 KiB), plaquette partial sums (at most
  * 32 KiB per layer), Polyakov partial sums (16 bytes per 256 sites of a time
  * slice, per layer) and the partial sums of the measured passes of
- * su3_sweep_measure (24 bytes per 64 links of one pass on a single torus,
- * 48 bytes per 256 on a double-layered torus).
+ * su3_sweep_measure (3 passes x nlat doubles per 64 links of one pass:
+ * 24 bytes on a single torus, 48 on a double-layered torus).
  * SU3_EINVAL on invalid parameters. */
 su3_status su3_footprint(const su3_params *p, size_t *link_bytes, size_t *scratch_bytes);
 
@@ -121,8 +121,10 @@ su3_status su3_sweep(su3_ctx *c, int32_t n, double beta);
  * staple terms of the directions nu < mu, which is the final plaquette sum of
  * the planes (nu, mu), nu < mu; the three passes give all six planes.  On a
  * double-layered torus a plaquette based at x - nu lies in the other layer
- * than x when that step crosses a flipped boundary; one more kernel sums
- * those plaquettes so that each is filed under its base site's layer.  The
+ * than x when that step crosses a flipped boundary; the measured passes sum
+ * those lower terms separately and file them under that layer, so that each
+ * plaquette counts for its base site's layer.  One small kernel per sweep adds
+ * the per-workgroup sums in a fixed order.  The
  * value equals su3_plaquette's up to rounding (products in the link
  * precision, before the final reunitarisation of the new link; sums in
  * FP64).  SU3_ENUMERIC (outputs written) if a measured plaquette is not
@@ -213,8 +215,9 @@ su3_status su3_set_sweep_index(su3_ctx *c, uint64_t sweep_index);
  * bath, 97.2 % at beta = 5.7 (Sec. 2.1); kp_accepts / kp_attempts is that
  * rate.  Every SU(2) subgroup of every updated link makes nhit attempts at
  * most and stops at its first acceptance, so with nhit = 1 kp_attempts is
- * exactly 3 x 4 V nlat per sweep.  Any pointer may be NULL.  Synchronises the
- * stream. */
+ * 3 x 4 V nlat per sweep, less one for every subgroup whose staple projection
+ * vanishes exactly (k = 0: nothing to sample, no attempt).  Any pointer may be
+ * NULL.  Synchronises the stream. */
 su3_status su3_counters(su3_ctx *c, uint64_t *sweeps, uint64_t *kp_attempts, uint64_t *kp_accepts);
 
 /* Random gauge transformation U_mu(x) -> g(x) U_mu(x) g(x+mu)^+ with Haar g
