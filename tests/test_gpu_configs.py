@@ -44,8 +44,14 @@ def _binned(x, nbins=20):
     return x.mean(), b.std(ddof=1) / np.sqrt(nbins)
 
 
-@pytest.mark.parametrize("L,nlat", [(16, 1), ((8, 8, 8, 16), 2)])
+@pytest.mark.parametrize("L,nlat", [(16, 1), ((8, 8, 8, 16), 2), (32, 1)])
 def test_fp32_first_sweeps_against_fp64_oracle(hb, L, nlat):
+    """The FP32 tier against the FP64 oracle, the whole lattice: four sweeps,
+    two at 32^4 (the benchmark's FP32 size), whose 12.6 million accept
+    decisions per sweep already include a few hundred that FP32 takes the
+    other way in the first sweep (reading of the plaquette bound: it holds up
+    to the onset of such flips, here still well inside 1e-5 by the volume
+    average)."""
     from oracle import su3ref
 
     _say(f"fp32 first sweeps L={L} nlat={nlat}")
@@ -53,7 +59,7 @@ def test_fp32_first_sweeps_against_fp64_oracle(hb, L, nlat):
     ref = su3ref.Oracle(L, nlat=nlat, seed=5)
     lat.start(True)
     ref.start(True)
-    for s in range(4):
+    for s in range(2 if L == 32 else 4):
         lat.sweep(1, 5.7)
         ref.sweep(1, 5.7)
         p32, p64 = lat.plaquette(), ref.plaquette()
