@@ -503,6 +503,21 @@ template <typename R> __device__ __forceinline__ M3<R> mul_nd_su3(const M3<R> &A
     rebuild_row2(C);
     return C;
 }
+// A^+ B
+template <typename R> __device__ __forceinline__ M3<R> mul_dn_su3(const M3<R> &A, const M3<R> &B)
+{
+    M3<R> C;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            Cx<R> t = cmul_cn(A.e[0][a], B.e[0][b]);
+            t = cmadd_cn(t, A.e[1][a], B.e[1][b]);
+            C.e[a][b] = cmadd_cn(t, A.e[2][a], B.e[2][b]);
+        }
+    rebuild_row2(C);
+    return C;
+}
 // C += A
 template <typename R> __device__ __forceinline__ void add_to(M3<R> &C, const M3<R> &A)
 {

@@ -18,6 +18,7 @@ constexpr int kEntries = 6;
 constexpr int kBlock = 256;          // threads per workgroup (4 waves of 64)
 constexpr int kPassBlock = 64;       // threads per workgroup of the one-wave pass kernels
 constexpr int kPlaqBlocksMax = 4096; // workgroups per layer of the plaquette reduction
+constexpr int kPlaqWalkBlock = 256;  // threads per workgroup of the plaquette walk
 constexpr int kCounterSlots = 4096;  // heat-bath counter slots (pairs of u64: attempts, accepts)
 constexpr int kNumXcd = 8;           // MI355X: 8 XCDs, workgroup b runs on XCD b % 8
 constexpr int kMeasureChunk = 256;   // sweeps per read-back of su3_sweep_measure
@@ -77,5 +78,29 @@ struct Geom {
     int nd1;            // L1 / w1
     FastDiv dl0h, dl1, dl2, dl3, dw1, dw2, dnd1;  // division by L0/2, L1, L2, L3, w1, w2, nd1
 };
+
+// Column order of the plaquette walk.  Thread w (0 <= w < nch L0 L1 L2) of a
+// layer takes the column (x0, x1, x2) and the chunk c of x3 with
+//   w = (d nch + c) S + x0 + L0 (x1' + w1 x2'),  S = L0 w1 w2,
+// d the domain of (x1, x2) numbered as in the pass order (x1 = (d mod nd1) w1
+// + x1', x2 = (d / nd1) w2 + x2').  So an XCD's contiguous range of threads
+// covers whole domains with all their chunks, and the lanes of a wave cover
+// consecutive x0.  Chunk c covers x3 in [c L3 / nch, (c + 1) L3 / nch).
+// Returns c and fills x[0..2].
+constexpr int walk_column(const Geom &g, int nch, int w, int x[3])
+{
+    const int a = div_by(w >> 1, g.dl0h);  // floor(w / L0) = floor(floor(w / 2) / (L0 / 2))
+    x[0] = w - a * g.L[0];
+    const int b = div_by(a, g.dw1);
+    const int x1p = a - b * g.w1;
+    const int q = div_by(b, g.dw2);
+    const int x2p = b - q * g.w2;
+    const int d = q / nch;
+    const int c = q - d * nch;
+    const int d2 = div_by(d, g.dnd1);
+    x[1] = (d - d2 * g.nd1) * g.w1 + x1p;
+    x[2] = d2 * g.w2 + x2p;
+    return c;
+}
 
 }  // namespace su3hb

@@ -1184,6 +1184,110 @@ __global__ __launch_bounds__(kBlock, 2) void k_plaq_sites(const store_t<R> *__re
     }
 }
 
+// Re Tr P Q^+ of two SU(3) matrices given by rows 0 and 1 (row 2 rebuilt).
+__device__ __forceinline__ double retr_pq12(M3<double> P, M3<double> Q)
+{
+    rebuild_row2(P);
+    rebuild_row2(Q);
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) s += P.e[a][b].re * Q.e[a][b].re + P.e[a][b].im * Q.e[a][b].im;
+    return s;
+}
+
+// One column of the plaquette walk: the sites (x0, x1, x2, x3) of the
+// thread's chunk [x3a, x3b) of x3, in increasing x3.  At each site the four
+// own links are loaded once (and checked); the planes (mu, nu), nu < 3, take
+// the links of the forward neighbours x + mu in the same x3 slab.  A plane
+// (mu, 3) needs U_mu(x + 3), the next site's own link:
+//   Re Tr U_mu(x) U_3(x + mu) U_mu(x + 3)^+ U_3(x)^+ = Re Tr M_mu U_mu(x + 3)^+,
+//   M_mu = U_3(x)^+ U_mu(x) U_3(x + mu),
+// so M_mu (rows 0, 1) is formed at x and carried to the next site.  Every
+// link is then read as an own link and by its three backward neighbours in
+// the same step of the walk, each own link is loaded and checked once, and
+// only the last site of a chunk reads links of the slab above it.
+// Summation order: fixed per thread.
+template <typename R, bool DLT>
+__device__ __forceinline__ double plaq_column(const store_t<R> *__restrict__ links, const Geom &g, int layer,
+                                              int nch, int w, double tol, int &bad)
+{
+    int x[4];
+    const int c = walk_column(g, nch, w, x);
+    const int x3a = (int)((long long)c * g.L[3] / nch), x3b = (int)((long long)(c + 1) * g.L[3] / nch);
+    const int lbase = DLT ? layer * g.Vh : 0;
+    M3<double> M0, M1, M2;
+    double s = 0.0;
+    for (int x3 = x3a; x3 < x3b; ++x3) {
+        x[3] = x3;
+        const int par = (x[0] + x[1] + x[2] + x3) & 1, opp = par ^ 1;
+        const int n = lbase + (lex_of(g, x) >> 1);
+        const M3<double> U0 = load_rows01<R>(planes<R>(links, g, 0, par), n);
+        const M3<double> U1 = load_rows01<R>(planes<R>(links, g, 1, par), n);
+        const M3<double> U2 = load_rows01<R>(planes<R>(links, g, 2, par), n);
+        M3<double> U3 = load_rows01<R>(planes<R>(links, g, 3, par), n);
+        bad += link_bad(U0, tol) + link_bad(U1, tol) + link_bad(U2, tol) + link_bad(U3, tol);
+        if (x3 > x3a) {
+            // planes (mu, 3) of the site below
+            s += retr_pq12(M0, U0);
+            s += retr_pq12(M1, U1);
+            s += retr_pq12(M2, U2);
+        }
+        const int e0 = nbr_elem<0, +1, 0, 0, DLT>(g, x, layer);
+        const int e1 = nbr_elem<1, +1, 0, 0, DLT>(g, x, layer);
+        const int e2 = nbr_elem<2, +1, 0, 0, DLT>(g, x, layer);
+        rebuild_row2(U3);
+        s += retr_pq12(mul_nn_su3(U0, convert<double>(load_link12<R>(planes<R>(links, g, 1, opp), e0))),
+                       mul_nn_su3(U1, convert<double>(load_link12<R>(planes<R>(links, g, 0, opp), e1))));
+        s += retr_pq12(mul_nn_su3(U0, convert<double>(load_link12<R>(planes<R>(links, g, 2, opp), e0))),
+                       mul_nn_su3(U2, convert<double>(load_link12<R>(planes<R>(links, g, 0, opp), e2))));
+        M0 = mul_dn_su3(U3, mul_nn_su3(U0, convert<double>(load_link12<R>(planes<R>(links, g, 3, opp), e0))));
+        s += retr_pq12(mul_nn_su3(U1, convert<double>(load_link12<R>(planes<R>(links, g, 2, opp), e1))),
+                       mul_nn_su3(U2, convert<double>(load_link12<R>(planes<R>(links, g, 1, opp), e2))));
+        M1 = mul_dn_su3(U3, mul_nn_su3(U1, convert<double>(load_link12<R>(planes<R>(links, g, 3, opp), e1))));
+        M2 = mul_dn_su3(U3, mul_nn_su3(U2, convert<double>(load_link12<R>(planes<R>(links, g, 3, opp), e2))));
+    }
+    if (x3b > x3a) {
+        // planes (mu, 3) of the chunk's last site: the links of the slab above
+        x[3] = x3b - 1;
+        const int opp = ((x[0] + x[1] + x[2] + x[3]) & 1) ^ 1;
+        const int e3 = nbr_elem<3, +1, 0, 0, DLT>(g, x, layer);
+        s += retr_pq12(M0, load_rows01<R>(planes<R>(links, g, 0, opp), e3));
+        s += retr_pq12(M1, load_rows01<R>(planes<R>(links, g, 1, opp), e3));
+        s += retr_pq12(M2, load_rows01<R>(planes<R>(links, g, 2, opp), e3));
+    }
+    return s;
+}
+
+// Plaquette of large FP64 lattices by walking x3: grid (nblk, nlat),
+// workgroup b (XCD-remapped) takes the threads [b T, (b+1) T) of the column
+// order (walk_column), T = tiles_per_block kPlaqWalkBlock.  Output as
+// k_plaq_partial.  At 32^4 (4 chunks of 8, two waves per SIMD): 143 us
+// against 166 us for one site per thread; at 24^4 53 against 70 us.
+template <typename R, bool DLT>
+__global__ __launch_bounds__(kPlaqWalkBlock, 2) void k_plaq_walk(const store_t<R> *__restrict__ links, const Geom g,
+                                                                 const int nch, const int tiles_per_block,
+                                                                 const double tol, double *__restrict__ partials)
+{
+    const int layer = DLT ? (int)blockIdx.y : 0;
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const int nthreads = g.L[0] * g.L[1] * g.L[2] * nch;
+    double s = 0.0;
+    int bad = 0;
+    for (int t = 0; t < tiles_per_block; ++t) {
+        const int w = (b * tiles_per_block + t) * kPlaqWalkBlock + threadIdx.x;
+        if (w < nthreads) s += plaq_column<R, DLT>(links, g, layer, nch, w, tol, bad);
+    }
+    const double bs = block_sum<kPlaqWalkBlock>(s);
+    __syncthreads();
+    const double bb = block_sum<kPlaqWalkBlock>((double)bad);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.y * gridDim.x + blockIdx.x] = bs;
+        partials[(gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = bb;
+    }
+}
+
 // Double-layered torus: per-layer plaquette sums of a measured sweep from the
 // nmeas pairs (layer 0, layer 1) of the three measured passes, fixed order:
 // sums[1 + l] = the sum of layer l, sums[0] = sums[1] + sums[2].
@@ -1424,10 +1528,26 @@ hipError_t launch_measure_final(const double *meas, const Geom &g, int lanes, do
 hipError_t launch_plaquette(int precision, const void *links, const Geom &g, double *partials, double *sums,
                             hipStream_t s, double *mean)
 {
-    const int nblk = plaq_blocks(g);
-    const dim3 grid(nblk, g.nlat);
     const bool dlt = g.nlat == 2;
     const double tol = unitarity_tol(precision);
+    const int nch = plaq_walk_chunks(g, precision);
+    if (nch > 0) {
+        // FP64 lattices with enough columns: the x3 walk
+        const int nblk = plaq_walk_blocks(g, nch);
+        const dim3 grid(nblk, g.nlat);
+        const long long tiles = ((long long)g.L[0] * g.L[1] * g.L[2] * nch + kPlaqWalkBlock - 1) / kPlaqWalkBlock;
+        const int tpb = (int)((tiles + nblk - 1) / nblk);
+        if (dlt)
+            k_plaq_walk<double, true><<<grid, kPlaqWalkBlock, 0, s>>>((const double2 *)links, g, nch, tpb, tol,
+                                                                      partials);
+        else
+            k_plaq_walk<double, false><<<grid, kPlaqWalkBlock, 0, s>>>((const double2 *)links, g, nch, tpb, tol,
+                                                                       partials);
+        k_plaq_final<<<1, kBlock, 0, s>>>(partials, nblk, g.nlat, sums, mean, 36.0 * (double)g.Vh);
+        return hipGetLastError();
+    }
+    const int nblk = plaq_blocks(g);
+    const dim3 grid(nblk, g.nlat);
     if (precision == 64) {
         // one site per thread: tiles of kBlock sites
         const long long tiles = (2LL * g.Vh + kBlock - 1) / kBlock;

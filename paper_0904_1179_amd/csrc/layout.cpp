@@ -142,6 +142,30 @@ int plaq_blocks(const Geom &g)
     return (int)(need < kPlaqBlocksMax ? need : kPlaqBlocksMax);
 }
 
+// The plaquette walk (one thread per column and chunk of x3, which reads
+// each link as an own link and as a neighbour in the same step of the walk)
+// takes FP64 lattices with enough columns for one wave per SIMD (65536
+// threads on the 1024 SIMDs) in chunks of at least kPlaqWalkMinSteps sites,
+// aiming at two waves per SIMD (kPlaqWalkThreads).  Smaller lattices, and
+// FP32 links (k_plaq_partial, faster there), take the per-site kernels.
+constexpr long long kPlaqWalkThreads = 131072, kPlaqWalkMinThreads = 65536, kPlaqWalkMinSteps = 4;
+
+int plaq_walk_chunks(const Geom &g, int precision)
+{
+    if (precision != 64) return 0;
+    const long long cols = (long long)g.nlat * g.L[0] * g.L[1] * g.L[2];
+    long long nch = ceil_div(kPlaqWalkThreads, cols);
+    if (nch > g.L[3] / kPlaqWalkMinSteps) nch = g.L[3] / kPlaqWalkMinSteps;
+    return nch >= 1 && cols * nch >= kPlaqWalkMinThreads ? (int)nch : 0;
+}
+
+int plaq_walk_blocks(const Geom &g, int nch)
+{
+    const long long need = ceil_div((long long)g.L[0] * g.L[1] * g.L[2] * nch, kPlaqWalkBlock);
+    const int most = plaq_blocks(g);
+    return (int)(need < most ? need : most);
+}
+
 int meas_blocks(const Geom &g, int lanes) { return pass_blocks(g, pass_links_per_block(g, lanes)); }
 
 // the most workgroups a measured pass can have: 64 links per workgroup

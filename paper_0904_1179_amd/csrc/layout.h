@@ -35,8 +35,14 @@ int lanes_per_link(const Geom &g, int nhit, int requested);
 int pass_links_per_block(const Geom &g, int lanes);
 // workgroups covering the nlat * Vh links of one pass, nb links each
 int pass_blocks(const Geom &g, int nb);
-// plaquette reduction: workgroups per layer
+// plaquette reduction: workgroups per layer (the most any plaquette kernel uses)
 int plaq_blocks(const Geom &g);
+// Chunks of x3 per column of the plaquette walk (k_plaq_walk) for links of
+// the given precision, or 0 where the per-site kernels run instead (FP32, and
+// lattices too small to walk).
+int plaq_walk_chunks(const Geom &g, int precision);
+// workgroups per layer of the plaquette walk with nch chunks (<= plaq_blocks)
+int plaq_walk_blocks(const Geom &g, int nch);
 // workgroups of a measured pass of su3_sweep_measure with `lanes` lanes per link
 int meas_blocks(const Geom &g, int lanes);
 // Polyakov loops: workgroups per layer

@@ -2,7 +2,7 @@
 // under the address and undefined-behaviour sanitizers: parameter validation,
 // the pass order's domains, invariant division, buffer sizes and scratch
 // offsets, the index maps between the tiled store and canonical link ids,
-// and the link packing round trip.
+// the column order of the plaquette walk, and the link packing round trip.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -135,6 +135,37 @@ static void layout_case(const su3_params &p, std::mt19937_64 &rng)
     CHECK(same, "pack/unpack round trip differs");
 }
 
+// the plaquette walk: every (column, chunk) exactly once, chunks partitioning
+// x3, and a grid that covers the threads within the partials' room
+static void walk_case(const su3_params &p, int nch)
+{
+    const Geom g = make_geom(&p);
+    const long long cols = (long long)p.L[0] * p.L[1] * p.L[2], n = cols * nch;
+    std::vector<char> seen((size_t)n, 0);
+    for (long long w = 0; w < n; ++w) {
+        int x[3] = {-1, -1, -1};
+        const int c = walk_column(g, nch, (int)w, x);
+        const bool ok = c >= 0 && c < nch && x[0] >= 0 && x[0] < p.L[0] && x[1] >= 0 && x[1] < p.L[1] && x[2] >= 0 &&
+                        x[2] < p.L[2];
+        CHECK(ok, "walk_column out of range at w = %lld", w);
+        if (!ok) continue;
+        const long long k = (long long)c * cols + x[0] + (long long)p.L[0] * (x[1] + (long long)p.L[1] * x[2]);
+        CHECK(!seen[(size_t)k], "walk_column reaches a column and chunk twice");
+        seen[(size_t)k] = 1;
+    }
+    long long covered = 0;
+    for (int c = 0; c < nch; ++c) {
+        const long long a = (long long)c * p.L[3] / nch, b = (long long)(c + 1) * p.L[3] / nch;
+        CHECK(a == covered && b > a, "chunk %d of %d", c, nch);
+        covered = b;
+    }
+    CHECK(covered == p.L[3], "chunks do not cover x3");
+    const int nblk = plaq_walk_blocks(g, nch);
+    const long long tiles = (n + kPlaqWalkBlock - 1) / kPlaqWalkBlock, tpb = (tiles + nblk - 1) / nblk;
+    CHECK(nblk >= 1 && nblk <= plaq_blocks(g), "walk workgroups %d, room for %d", nblk, plaq_blocks(g));
+    CHECK(tpb * nblk * kPlaqWalkBlock >= n, "walk grid does not cover its threads");
+}
+
 int main()
 {
     std::mt19937_64 rng(1);
@@ -160,6 +191,22 @@ int main()
                                 params(16, 16, 16, 16, 2, 0x7, 64), params(256, 256, 128, 128, 1, 0, 32),
                                 params(1024, 2, 2, 256, 2, 0x3, 64)};
     for (const su3_params &p : large) geometry_case(p, rng);
+    // plaquette walk: the chunk counts the library picks, and forced ones on
+    // small and ragged lattices
+    for (const su3_params &p : large) {
+        const Geom g = make_geom(&p);
+        for (int prec : {64, 32}) {
+            const int nch = plaq_walk_chunks(g, prec);
+            if (p.L[0] == 16) CHECK(nch == 0, "2 x 16^4 walks");
+            if (p.L[0] == 32) CHECK(nch == (prec == 64 ? 4 : 0), "32^4 walks in %d chunks", nch);
+            if (nch > 0) {
+                CHECK(p.L[3] / nch >= 4, "chunks shorter than 4 sites");
+                walk_case(p, nch);
+            }
+        }
+    }
+    for (const su3_params &p : small)
+        for (int nch = 1; nch <= p.L[3]; ++nch) walk_case(p, nch);
     // invariant division: every divisor up to 4096 on dividends around its multiples
     for (uint32_t d = 1; d <= 4096; ++d) {
         const FastDiv f = make_fastdiv(d);
