@@ -73,9 +73,9 @@ def test_walk_plaquette_matches_oracle_on_the_same_links(hb, L, nlat, flip, prec
 
 def test_walk_counts_failing_links(hb):
     """Bad links anywhere in the walk's order are each counted once: the
-    first link, a direction-3 link in the top slab (read by the last site of
-    a chunk as a neighbour, checked once as an own link), and a link of the
-    last site."""
+    first link (the first site of the first chunk), a U_3 link in the top
+    slab x3 = 31 (the last site of the last chunk, read there as an own link
+    and by three neighbours), and the last link of the lattice."""
     L = (32, 32, 32, 32)
     _say(f"plaquette walk failing links L={L}")
     lat = hb.Lattice(L, precision=64, seed=2)
