@@ -76,11 +76,11 @@ typedef struct {
  * Links: 8 blocks (4 directions x 2 parities) of round_up(nlat*V/2, 64) + 64
  * links, each link stored as its rows 0 and 1 (6 complex numbers of the link
  * precision).
- * Scratch: heat-bath counter slots (64 KiB), plaquette partial sums (at most
- * 32 KiB per layer), Polyakov partial sums (16 bytes per 256 sites of a time
- * slice, per layer) and the partial sums of the measured passes of
- * su3_sweep_measure (3 passes x nlat doubles per 64 links of one pass:
- * 24 bytes on a single torus, 48 on a double-layered torus).
+ * Scratch: heat-bath counter slots (64 KiB), plaquette partial sums and
+ * failing-link counts (at most 64 KiB per layer), Polyakov partial sums (16
+ * bytes per 256 sites of a time slice, per layer) and the partial sums of the
+ * measured passes of su3_sweep_measure (3 passes x nlat doubles per 64 links
+ * of one pass: 24 bytes on a single torus, 48 on a double-layered torus).
  * SU3_EINVAL on invalid parameters. */
 su3_status su3_footprint(const su3_params *p, size_t *link_bytes, size_t *scratch_bytes);
 
