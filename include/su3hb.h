@@ -238,7 +238,7 @@ su3_status su3_profile_read(su3_ctx *c, double *total_ms, uint64_t *passes);
 /* Lanes per link of the heat-bath passes.  By default (lanes = 0) a pass of
  * more than 32768 links runs one lane per link; smaller passes, which would
  * leave most of the GPU idle and take about one link update's latency, run 2
- * (up to 32768 links) or 4 (up to 16384) lanes per link that share the
+ * (up to 32768 links) or 4 (up to 8192) lanes per link that share the
  * staple directions and the random draws of the update (1-hit only).  The
  * result does not depend on the choice: every variant adds in the same order
  * and gives the same bits.  lanes = 1, 2 or 4 forces that count (2 and 4 need

@@ -117,8 +117,11 @@ size_t link_bytes_of(const su3_params *p, const Geom &g)
 // kLanes2Max with 2, larger ones with 1.  Measured per pass (FP64): 2048 links
 // 11.3 us with 1 lane, 9.3 us with 4; 32768 links about even (FP32: 13.5 vs
 // 11 us with 2); 65536 links (2 x 16^4) 19 us with 1 lane, 21 us with 2, whose
-// two waves per SIMD then issue 1.6 times the instructions of one.
-constexpr long long kLanes4Max = 16384, kLanes2Max = 32768;
+// two waves per SIMD then issue 1.6 times the instructions of one.  Per sweep,
+// 4 against 2 lanes: 2048 to 5000 links (8^4, 2 x 8^4, 10^4) 76-80 against
+// 83-85 us in FP64, even in FP32; 10368 links (12^4) 91 against 86 us in FP64,
+// 85 against 76 us in FP32.
+constexpr long long kLanes4Max = 8192, kLanes2Max = 32768;
 
 int lanes_per_link(const Geom &g, int nhit, int requested)
 {
