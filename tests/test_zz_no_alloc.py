@@ -3,7 +3,8 @@ su3_plaquette through the C ABI.  Both run the same plaquette kernels with the
 same reduction order, the one on the context's scratch buffer, the other on
 the library's own device array, so their values must agree bit for bit; two
 calls in a row, the second on a smaller lattice (the array keeps the first
-call's contents), and a lattice with a NaN link."""
+call's contents), a lattice large enough for the plaquette's x3 walk, and a
+lattice with a NaN link."""
 import numpy as np
 import pytest
 
@@ -47,6 +48,23 @@ def test_noalloc_plaquette_matches_context_plaquette(hb):
         assert got[1 + lat.nlat] == 0.0
     # the same lattice again after the small one: the array's old contents do not leak in
     assert np.array_equal(_noalloc(hb, big)[:3], big.plaquette())
+
+
+def test_noalloc_plaquette_on_the_walk_path(hb):
+    """A double-layered FP64 lattice large enough for the x3 walk of the
+    plaquette (32 x 32 x 16 x 16 per layer: 4 chunks of 4 sites, 65536 threads
+    per layer),
+    then a small lattice, then the large one again: bit for bit as
+    su3_plaquette each time."""
+    big = hb.Lattice((32, 32, 16, 16), nlat=2, flip_mask=0xF, seed=7)
+    big.start(True)
+    big.sweep(1, 5.7)
+    small = hb.Lattice((4, 6, 4, 4), nlat=2, seed=8)
+    small.start(True)
+    for lat in (big, small, big):
+        got = _noalloc(hb, lat)
+        assert np.array_equal(got[:3], lat.plaquette()), got
+        assert got[3] == 0.0
 
 
 def test_noalloc_plaquette_counts_bad_links(hb):
