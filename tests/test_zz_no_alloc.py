@@ -52,10 +52,9 @@ def test_noalloc_plaquette_matches_context_plaquette(hb):
 
 def test_noalloc_plaquette_on_the_walk_path(hb):
     """A double-layered FP64 lattice large enough for the x3 walk of the
-    plaquette (32 x 32 x 16 x 16 per layer: 4 chunks of 4 sites, 65536 threads
-    per layer),
-    then a small lattice, then the large one again: bit for bit as
-    su3_plaquette each time."""
+    plaquette (32 x 32 x 16 x 16 per layer: 4 chunks of 4 sites, 65536
+    threads per layer), then a small lattice, then the large one again: bit
+    for bit as su3_plaquette each time."""
     big = hb.Lattice((32, 32, 16, 16), nlat=2, flip_mask=0xF, seed=7)
     big.start(True)
     big.sweep(1, 5.7)
