@@ -150,6 +150,38 @@ def test_64_config_beta6_sampled(hb):
         del lat
 
 
+def test_64_config_beta6_every_link(hb):
+    """64^4, beta 6.0, FP64, hot start, seed 1 (the 64^4 configuration of the
+    benchmark): after one measured sweep every link against the oracle's full
+    sweep (<= 1e-12), the counters exactly, the fused plaquette and
+    su3_plaquette (the x3 walk, one chunk of 64 sites per column) <= 1e-13."""
+    from oracle import su3ref
+
+    L = (64, 64, 64, 64)
+    _say("64^4 beta 6.0 every link: GPU sweep")
+    lat = hb.Lattice(L, precision=64, seed=1)
+    lat.start(True)
+    fused = lat.sweep_measure(1, 6.0)[0]
+    got = lat.get_links()
+    _say("64^4 beta 6.0 every link: oracle start and sweep")
+    ref = su3ref.Oracle(L, seed=1)
+    ref.start(True)
+    ref.sweep(1, 6.0)
+    want = ref.links()
+    assert got.shape == want.shape
+    dlink = 0.0
+    chunk = 1 << 22
+    for i in range(0, len(got), chunk):
+        dlink = max(dlink, float(np.abs(got[i:i + chunk] - want[i:i + chunk]).max()))
+    del got
+    pref = ref.plaquette()
+    _say(f"  max |dU| = {dlink:.3e}, fused {fused}, oracle {pref}")
+    assert dlink < 1e-12
+    assert lat.counters()[1:] == ref.counters()
+    assert np.abs(fused - pref).max() <= 1e-13
+    assert np.abs(lat.plaquette() - pref).max() <= 1e-13
+
+
 def test_size_limit_fp32_sampled(hb):
     """The largest lattice the library accepts, 2^30 sites (256 x 256 x 128 x
     128, FP32 links: 206 GB of HBM; link offsets far beyond 2^31 elements):
