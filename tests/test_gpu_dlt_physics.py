@@ -20,7 +20,8 @@ def hb():
 
 
 @pytest.mark.parametrize("L,mask,b0,b1,nhit", [((4, 4, 4, 6), 0x7, 5.5, 6.2, 1), ((6, 4, 4, 4), 0xF, 0.8, 6.0, 1),
-                                               ((4, 4, 4, 4), 0x7, 5.7, 5.7, 2), ((8, 8, 8, 4), 0x7, 6.2, 5.5, 1)])
+                                               ((4, 4, 4, 4), 0x7, 5.7, 5.7, 2), ((8, 8, 8, 4), 0x7, 6.2, 5.5, 1),
+                                               ((16, 16, 16, 16), 0x7, 5.5, 6.2, 1)])  # the benchmark's lattice
 def test_two_couplings_match_oracle(hb, L, mask, b0, b1, nhit):
     from oracle import su3ref
 
@@ -34,6 +35,7 @@ def test_two_couplings_match_oracle(hb, L, mask, b0, b1, nhit):
         assert np.abs(lat.get_links() - ref.links()).max() < 1e-12, f"sweep {s + 1}"
         assert np.abs(lat.plaquette() - ref.plaquette()).max() < 1e-13
         assert lat.counters()[1:] == ref.counters()
+    assert np.abs(lat.polyakov() - ref.polyakov()).max() < 1e-13
 
 
 def test_two_couplings_rejected_on_single_torus(hb):
